@@ -1,0 +1,169 @@
+/*
+ * trs.h -- C-ABI of the MI355X term-rewriting library (libtrs.so).
+ *
+ * The library computes innermost normal forms of ground terms for a
+ * left-linear term rewrite system, following the problem statement of
+ * "Term Rewriting on GPUs" (van Eerd, Groote, Hijma, Martens, Wijs):
+ *
+ *   - terms, substitutions, matches and normal forms: Section 2,
+ *     Definitions 1 and 2; a rule l -> r requires l not a variable,
+ *     Var(r) a subset of Var(l), and every variable at most once in l;
+ *   - strategy: innermost; for a head symbol the rules are tried in their
+ *     given order and the first match is applied (Section 2, the derive and
+ *     rewrite_f procedures);
+ *   - method: Section 3 -- the term graph is stored as arrays indexed by a
+ *     node index (head symbols, argument indices, normal-form flags,
+ *     reference counts); in lock-step rounds every stored node whose
+ *     arguments are all in normal form is matched and rewritten in place,
+ *     followed by reference-count garbage collection with free-index reuse,
+ *     until a round sees no node that is not in normal form.
+ *
+ * Encoding (all integers little-endian int32 unless stated):
+ *   - symbols are numbered 0..n_sym-1; arity[s] is the arity of symbol s;
+ *   - a term is its prefix (pre-order) sequence of symbol ids;
+ *   - rule i occupies rule_code[rule_off[i] .. rule_off[i+1]): the prefix code
+ *     of its left-hand side immediately followed by that of its right-hand
+ *     side; variable k of the rule is written -1-k;
+ *   - the normal form read back is the canonical serialisation: the prefix
+ *     sequence of symbol ids of the term with all sharing expanded.
+ *
+ * Call order: trs_create -> trs_load_rules -> trs_load_terms -> trs_normalize
+ * -> trs_read_nf (any number of times) ; trs_load_terms may be called again
+ * to start over with new terms.  A context is used by one host thread at a
+ * time; device work is issued on the stream given in trs_config.
+ *
+ * Errors: every call returns TRS_OK (0) or a negative trs_status; the last
+ * error message of a context is available from trs_last_error().  No call
+ * aborts the process.
+ */
+#ifndef TRS_H
+#define TRS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t trs_status;
+
+#define TRS_OK 0
+#define TRS_E_ARG (-1)     /* null pointer, bad size, bad option value */
+#define TRS_E_STATE (-2)   /* call out of order (e.g. normalize before terms) */
+#define TRS_E_RULE (-3)    /* rule violates Definition 1 or left-linearity, or
+                              arity mismatch / arity above maxarity */
+#define TRS_E_TERM (-4)    /* input not ground, malformed prefix code */
+#define TRS_E_POOL (-5)    /* node pool exhausted (initial load or rewriting) */
+#define TRS_E_ROUNDS (-6)  /* max_rounds reached without a normal form */
+#define TRS_E_HIP (-7)     /* HIP runtime error (message in trs_last_error) */
+#define TRS_E_LIMIT (-8)   /* a rule exceeds the compiled-table limits */
+#define TRS_E_INTERNAL (-9)
+
+/* compiled-table limits (per rule / per system) */
+#define TRS_MAX_ARITY 8
+#define TRS_MAX_PATTERN 8   /* left-hand-side nodes below the root */
+#define TRS_MAX_NEW 8       /* right-hand-side nodes created per rewrite */
+#define TRS_MAX_RULES 256
+#define TRS_MAX_SYMBOLS 4096
+
+typedef struct trs_ctx trs_ctx;
+
+typedef struct {
+  int64_t pool_slots;  /* N: node slots in the pool (slot 0 is reserved) */
+  int32_t maxarity;    /* A: argument stride of the pool, 1..5;
+                          0 = take the highest arity of the loaded system */
+  int32_t device;      /* HIP device ordinal */
+  void *hip_stream;    /* hipStream_t on which all device work is issued;
+                          NULL = the library creates its own stream */
+  void *dev_mem;       /* optional caller-owned device block to carve the pool
+                          from (must stay valid while the context lives);
+                          NULL = the library allocates */
+  int64_t dev_bytes;   /* size of dev_mem in bytes */
+} trs_config;
+
+#define TRS_MODE_PLAIN 0     /* full sweep of every slot every round */
+#define TRS_MODE_FRONTIER 1  /* sweep a compacted frontier; full confirmation
+                                sweep before declaring a normal form */
+#define TRS_MODE_LEARNED 2   /* frontier filtered by the trained MLP */
+
+typedef struct {
+  int32_t mode;              /* TRS_MODE_* */
+  int32_t block;             /* threads per workgroup: 64..1024, multiple of
+                                64; 0 = tuned default */
+  int32_t nodes_per_thread;  /* slots swept per thread per tile: 1,2,4,8,16;
+                                0 = tuned default */
+  int32_t rounds_per_poll;   /* rounds issued between host checks of the
+                                device done flag; 0 = adaptive */
+  int64_t max_rounds;        /* 0 = unlimited; else TRS_E_ROUNDS past it */
+  float threshold;           /* learned mode: keep a node when p >= threshold */
+  int32_t persistent;        /* 1 = one cooperative persistent kernel runs the
+                                rounds with device-wide barriers; 0 = one
+                                launch per round (captured in a HIP graph) */
+  int32_t trace;             /* 1 = log per-(node, round) feature records
+                                (for training the frontier predictor) */
+} trs_opts;
+
+typedef struct {
+  int64_t rounds;        /* rewrite rounds until the confirmation round */
+  int64_t rule_apps;     /* rule applications (the paper's rewritten terms) */
+  int64_t node_visits;   /* slots examined, summed over rounds */
+  int64_t active_visits; /* visited slots that were live and not in normal form */
+  int64_t allocs;        /* nodes created */
+  int64_t frees;         /* nodes returned to the free list */
+  int64_t peak_slots;    /* highest slot extent n reached */
+  int64_t gc_rounds;     /* rounds that collected at least one node */
+  int64_t mlp_evals;     /* learned mode: predictor evaluations */
+  int64_t full_sweeps;   /* frontier modes: full confirmation sweeps */
+  int64_t launches;      /* kernel launches issued for the round loop */
+  double device_ms;      /* device time of the round loop (HIP events) */
+} trs_stats;
+
+/* Create a context.  No device memory is touched until trs_normalize, so rule
+ * and term validation also work on a host without a GPU. */
+trs_status trs_create(trs_ctx **out, const trs_config *cfg);
+void trs_destroy(trs_ctx *ctx);
+
+/* Load and compile the rewrite system (Section 2, Definition 1; rule order is
+ * the matching priority).  Inputs are copied; the caller keeps ownership.
+ * Validates: lhs not a variable, Var(rhs) within Var(lhs), left-linear lhs,
+ * well-formed prefix codes, arities within maxarity; compiles per-symbol
+ * decision tables (TRS_E_LIMIT beyond the TRS_MAX_* limits). */
+trs_status trs_load_rules(trs_ctx *ctx, int32_t n_sym, const int32_t *arity, int32_t n_rules,
+                          const int32_t *rule_off, const int32_t *rule_code, int64_t code_len);
+
+/* Load the ground input terms (prefix codes; term t occupies
+ * term_code[term_off[t] .. term_off[t+1]) ).  Inputs are copied.  Every term
+ * gets its own root entry; the terms share one node pool.  TRS_E_POOL if the
+ * initial graph does not fit in pool_slots - 1 slots. */
+trs_status trs_load_terms(trs_ctx *ctx, int32_t n_terms, const int64_t *term_off,
+                          const int32_t *term_code, int64_t code_len);
+
+/* Normalise all loaded terms on the device.  stats may be NULL.  On
+ * TRS_E_POOL / TRS_E_ROUNDS the pool contents are unspecified and the terms
+ * must be loaded again. */
+trs_status trs_normalize(trs_ctx *ctx, const trs_opts *opts, trs_stats *stats);
+
+/* Read back the normal form of term term_id as its canonical serialisation.
+ * With buf == NULL only *len_out is set.  TRS_E_ARG if cap < length. */
+trs_status trs_read_nf(trs_ctx *ctx, int32_t term_id, int32_t *buf, int64_t cap,
+                       int64_t *len_out);
+
+/* Rule applications per rule of the last trs_normalize (out[0..n_rules)). */
+trs_status trs_rule_counts(trs_ctx *ctx, int64_t *out, int32_t cap);
+
+/* Device bytes a context with this pool size and maxarity needs when the
+ * caller supplies dev_mem (trs_config.dev_mem / dev_bytes).  Pure host
+ * arithmetic; returns -1 for invalid sizes. */
+int64_t trs_device_bytes(int64_t pool_slots, int32_t maxarity);
+
+/* Default options (mode plain, tuned block and nodes per thread). */
+void trs_default_opts(trs_opts *opts);
+
+const char *trs_status_str(trs_status s);
+const char *trs_last_error(trs_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TRS_H */

@@ -1,0 +1,815 @@
+// trs_host.cpp -- host runtime of libtrs: context, rule compiler, term
+// loader, round driver and read-back behind the C-ABI of include/trs.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstring>
+#include <functional>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "trs.h"
+#include "trs_kernels.h"
+#include "trs_layout.h"
+
+namespace {
+
+const char *kStatusText[] = {"ok",         "bad argument", "call out of order", "invalid rule",
+                             "invalid term", "node pool exhausted", "round limit reached",
+                             "HIP runtime error", "compiled-table limit exceeded",
+                             "internal error"};
+
+}  // namespace
+
+struct trs_ctx {
+  trs_config cfg{};
+  int A = 0;
+  std::string err;
+
+  // rewrite system
+  bool rules_loaded = false;
+  int n_sym = 0, n_rules = 0;
+  std::vector<int32_t> arity;
+  std::vector<uint8_t> has_rules;
+  std::vector<int32_t> tab;
+
+  // input terms (host image of the initial pool, slots 0 .. n_init-1)
+  bool terms_loaded = false;
+  int n_terms = 0;
+  std::vector<int32_t> roots;
+  int64_t n_init = 0;
+  std::vector<int32_t> img_hss, img_args, img_rc;
+  std::vector<uint8_t> img_state;
+
+  // device side
+  bool dev_ready = false;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  Pool pool{};
+  Ctl *d_ctl = nullptr;
+  Ctl *h_ctl = nullptr;  // pinned
+  int32_t *d_tab = nullptr;
+  unsigned long long *d_bar = nullptr;
+  std::vector<void *> owned;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  int cu_count = 0;
+  unsigned long long *h_zero = nullptr;  // pinned zero for barrier resets
+  // captured chunk of rounds (one launch per round)
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  int g_grid = 0, g_block = 0, g_npt = 0, g_k = 0;
+  size_t g_lds = 0;
+
+  // results of the last normalisation
+  bool normalized = false;
+  int64_t n_final = 0;
+  std::vector<int64_t> rule_counts;
+  bool cache_valid = false;
+  std::vector<int32_t> c_hss, c_args;
+  std::vector<uint8_t> c_state;
+
+  trs_status fail(trs_status s, const std::string &msg) {
+    err = msg;
+    return s;
+  }
+};
+
+namespace {
+
+// ------------------------------------------------------------------ parsing
+
+// length of the prefix code starting at code[p] (variables, coded < 0, are
+// leaves); -1 if it runs past end or names an unknown symbol
+int64_t prefix_len(const std::vector<int32_t> &arity, const int32_t *code, int64_t p,
+                   int64_t end) {
+  int64_t need = 1, q = p;
+  while (need > 0) {
+    if (q >= end) return -1;
+    int32_t c = code[q++];
+    need--;
+    if (c >= 0) {
+      if (c >= (int32_t)arity.size()) return -1;
+      need += arity[c];
+    }
+  }
+  return q - p;
+}
+
+struct PNode {
+  int parent = -1, pos = 0, sym = -1, var = -1;
+  std::string key;
+};
+
+struct RNode {
+  int sym = -1, var = -1;
+  std::vector<int> kids;
+};
+
+std::string sym_key(int sym) { return "s" + std::to_string(sym); }
+std::string var_key(int var) { return "v" + std::to_string(var); }
+
+// build the pattern tree of a left-hand side given in prefix code
+bool parse_lhs(const std::vector<int32_t> &arity, const int32_t *c, int64_t len,
+               std::vector<PNode> &out) {
+  out.clear();
+  struct Fr {
+    int node, next, ar;
+  };
+  std::vector<Fr> st;
+  for (int64_t i = 0; i < len; i++) {
+    PNode pn;
+    if (!st.empty()) {
+      pn.parent = st.back().node;
+      pn.pos = st.back().next++;
+    }
+    if (c[i] < 0) {
+      pn.var = -1 - c[i];
+    } else {
+      pn.sym = c[i];
+    }
+    out.push_back(pn);
+    int me = (int)out.size() - 1;
+    if (c[i] >= 0 && arity[c[i]] > 0) st.push_back({me, 0, arity[c[i]]});
+    while (!st.empty() && st.back().next == st.back().ar) st.pop_back();
+  }
+  // canonical keys, children first (prefix order reversed)
+  std::vector<std::vector<int>> kids(out.size());
+  for (size_t k = 1; k < out.size(); k++) kids[out[k].parent].push_back((int)k);
+  for (int k = (int)out.size() - 1; k >= 0; k--) {
+    if (out[k].var >= 0) {
+      out[k].key = var_key(out[k].var);
+    } else {
+      std::string s = sym_key(out[k].sym) + "(";
+      for (size_t j = 0; j < kids[k].size(); j++) {
+        if (j) s += ",";
+        s += out[kids[k][j]].key;
+      }
+      out[k].key = s + ")";
+    }
+  }
+  return true;
+}
+
+void parse_rhs(const std::vector<int32_t> &arity, const int32_t *c, int64_t len,
+               std::vector<RNode> &out) {
+  out.clear();
+  struct Fr {
+    int node, ar;
+  };
+  std::vector<Fr> st;
+  for (int64_t i = 0; i < len; i++) {
+    RNode rn;
+    if (c[i] < 0)
+      rn.var = -1 - c[i];
+    else
+      rn.sym = c[i];
+    out.push_back(rn);
+    int me = (int)out.size() - 1;
+    if (!st.empty()) out[st.back().node].kids.push_back(me);
+    if (c[i] >= 0 && arity[c[i]] > 0) st.push_back({me, arity[c[i]]});
+    while (!st.empty() && (int)out[st.back().node].kids.size() == st.back().ar) st.pop_back();
+  }
+}
+
+std::string rhs_key(const std::vector<RNode> &R, int k) {
+  if (R[k].var >= 0) return var_key(R[k].var);
+  std::string s = sym_key(R[k].sym) + "(";
+  for (size_t j = 0; j < R[k].kids.size(); j++) {
+    if (j) s += ",";
+    s += rhs_key(R, R[k].kids[j]);
+  }
+  return s + ")";
+}
+
+struct Program {
+  std::vector<int32_t> words;  // program with offsets relative to its start
+};
+
+// Compile one rule into its table program.  Returns TRS_OK or an error with
+// a message in *msg.
+trs_status compile_rule(int rid, const std::vector<int32_t> &arity,
+                        const std::vector<uint8_t> &has_rules, const std::vector<PNode> &P,
+                        const std::vector<RNode> &R, Program &prog, std::string *msg) {
+  const int npat = (int)P.size() - 1;
+  if (npat > TRS_MAX_PATTERN) {
+    *msg = "rule " + std::to_string(rid) + ": left-hand side too large";
+    return TRS_E_LIMIT;
+  }
+  std::map<int, int> var_node;  // variable -> pattern node
+  std::map<std::string, int> lhs_sub;  // non-variable subterm key -> pattern node (k >= 1)
+  for (int k = 1; k <= npat; k++) {
+    if (P[k].var >= 0)
+      var_node[P[k].var] = k;
+    else if (!lhs_sub.count(P[k].key))
+      lhs_sub[P[k].key] = k;
+  }
+  struct NewNode {
+    int sym, rc;
+    bool nf;
+    std::vector<int> ops;
+  };
+  std::vector<NewNode> nn;
+  std::map<std::string, int> new_of;
+  std::vector<int> refs(npat + 1, 0);
+  // operand for RHS node k (not the root)
+  std::function<int(int)> operand = [&](int k) -> int {
+    if (R[k].var >= 0) {
+      int pnode = var_node.at(R[k].var);
+      refs[pnode]++;
+      return pnode;
+    }
+    std::string key = rhs_key(R, k);
+    auto it = lhs_sub.find(key);
+    if (it != lhs_sub.end()) {  // reuse the matched node of an equal lhs subterm
+      refs[it->second]++;
+      return it->second;
+    }
+    auto jt = new_of.find(key);
+    if (jt != new_of.end()) {  // equal subterms of one right-hand side are shared
+      nn[jt->second].rc++;
+      return -1 - jt->second;
+    }
+    NewNode x;
+    x.sym = R[k].sym;
+    x.rc = 1;
+    for (int ch : R[k].kids) x.ops.push_back(operand(ch));
+    bool nf = !has_rules[x.sym];
+    for (int o : x.ops) nf = nf && (o >= 1 || nn[-1 - o].nf);
+    x.nf = nf;
+    nn.push_back(x);
+    new_of[key] = (int)nn.size() - 1;
+    return -1 - ((int)nn.size() - 1);
+  };
+  bool var_root = R[0].var >= 0;
+  int rootpat = 0, rsym = -1;
+  std::vector<int> rops;
+  bool root_nf = false;
+  if (var_root) {
+    rootpat = var_node.at(R[0].var);
+    root_nf = true;
+  } else {
+    rsym = R[0].sym;
+    for (int ch : R[0].kids) rops.push_back(operand(ch));
+    root_nf = !has_rules[rsym];
+    for (int o : rops) root_nf = root_nf && (o >= 1 || nn[-1 - o].nf);
+  }
+  if ((int)nn.size() > TRS_MAX_NEW) {
+    *msg = "rule " + std::to_string(rid) + ": right-hand side creates too many nodes";
+    return TRS_E_LIMIT;
+  }
+  std::vector<std::pair<int, int>> pos, neg;
+  for (int k = 1; k <= npat; k++) {
+    int d = refs[k] - (P[k].parent == 0 ? 1 : 0);
+    if (d > 0) pos.push_back({k, d});
+    if (d < 0) neg.push_back({k, d});
+  }
+  std::vector<int32_t> &w = prog.words;
+  w.assign(6, 0);
+  w[0] = npat | ((int)nn.size() << 4) | ((int)var_root << 8) | ((int)root_nf << 9) |
+         ((int)pos.size() << 12) | ((int)neg.size() << 16) | (rootpat << 20);
+  w[1] = rsym;
+  w[5] = rid;
+  for (int k = 1; k <= npat; k++) {
+    int isvar = P[k].var >= 0;
+    w.push_back(P[k].parent | (P[k].pos << 4) | (isvar << 8) | ((isvar ? 0 : P[k].sym) << 16));
+  }
+  w[2] = (int32_t)w.size();
+  for (int o : rops) w.push_back(o);
+  w[3] = (int32_t)w.size();
+  for (auto &x : nn) {
+    w.push_back(x.sym | (x.rc << 16) | ((int)x.nf << 24));
+    for (int o : x.ops) w.push_back(o);
+  }
+  w[4] = (int32_t)w.size();
+  for (auto &pr : pos) w.push_back(pr.first | ((pr.second & 0xff) << 8));
+  for (auto &pr : neg) w.push_back(pr.first | ((pr.second & 0xff) << 8));
+  return TRS_OK;
+}
+
+#define HIPCHK(ctx, call)                                                              \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return (ctx)->fail(TRS_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+struct Piece {
+  void **dst;
+  size_t bytes;
+};
+
+// device arrays of a context, in carving order
+std::vector<Piece> device_pieces(trs_ctx *c, int64_t N, int A) {
+  const size_t state_pad = 1 << 16;  // vector loads of the last tile stay in bounds
+  return {
+      {(void **)&c->pool.hss, (size_t)N * 4},
+      {(void **)&c->pool.args, (size_t)N * A * 4},
+      {(void **)&c->pool.state, (size_t)N + state_pad},
+      {(void **)&c->pool.rc, (size_t)N * 4},
+      {(void **)&c->pool.fstack0, (size_t)N * 4},
+      {(void **)&c->pool.fstack1, (size_t)N * 4},
+      {(void **)&c->pool.dead0, (size_t)N * 4},
+      {(void **)&c->pool.dead1, (size_t)N * 4},
+      {(void **)&c->d_ctl, sizeof(Ctl)},
+      {(void **)&c->d_tab, (size_t)TAB_MAX_WORDS * 4},
+      {(void **)&c->d_bar, 256},
+  };
+}
+
+size_t carve_bytes(const std::vector<Piece> &pieces) {
+  size_t off = 0;
+  for (auto &pc : pieces) {
+    off = (off + 255) & ~(size_t)255;
+    off += pc.bytes;
+  }
+  return off;
+}
+
+trs_status device_init(trs_ctx *c) {
+  if (c->dev_ready) return TRS_OK;
+  HIPCHK(c, hipSetDevice(c->cfg.device));
+  hipDeviceProp_t prop;
+  HIPCHK(c, hipGetDeviceProperties(&prop, c->cfg.device));
+  c->cu_count = prop.multiProcessorCount;
+  if (c->cfg.hip_stream) {
+    c->stream = (hipStream_t)c->cfg.hip_stream;
+  } else {
+    HIPCHK(c, hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+    c->own_stream = true;
+  }
+  const int64_t N = c->cfg.pool_slots;
+  const int A = c->A;
+  std::vector<Piece> pieces = device_pieces(c, N, A);
+  if (c->cfg.dev_mem) {
+    size_t off = 0;
+    char *base = (char *)c->cfg.dev_mem;
+    for (auto &pc : pieces) {
+      off = (off + 255) & ~(size_t)255;
+      *pc.dst = base + off;
+      off += pc.bytes;
+    }
+    if (off > (size_t)c->cfg.dev_bytes)
+      return c->fail(TRS_E_ARG, "dev_mem too small: need " + std::to_string(off) + " bytes");
+  } else {
+    for (auto &pc : pieces) {
+      HIPCHK(c, hipMalloc(pc.dst, pc.bytes));
+      c->owned.push_back(*pc.dst);
+    }
+  }
+  c->pool.N = N;
+  HIPCHK(c, hipHostMalloc((void **)&c->h_ctl, sizeof(Ctl), hipHostMallocDefault));
+  HIPCHK(c, hipHostMalloc((void **)&c->h_zero, 64, hipHostMallocDefault));
+  std::memset(c->h_zero, 0, 64);
+  HIPCHK(c, hipEventCreate(&c->ev0));
+  HIPCHK(c, hipEventCreate(&c->ev1));
+  c->dev_ready = true;
+  return TRS_OK;
+}
+
+int default_block() { return 256; }
+int default_npt() { return 16; }
+
+}  // namespace
+
+// ======================================================================= ABI
+
+extern "C" {
+
+int64_t trs_device_bytes(int64_t pool_slots, int32_t maxarity) {
+  if (pool_slots < 2 || pool_slots > INT32_MAX || maxarity < 1 || maxarity > 5) return -1;
+  trs_ctx tmp;
+  return (int64_t)carve_bytes(device_pieces(&tmp, pool_slots, maxarity));
+}
+
+const char *trs_status_str(trs_status s) {
+  int i = -s;
+  if (i < 0 || i >= (int)(sizeof(kStatusText) / sizeof(kStatusText[0]))) return "unknown status";
+  return kStatusText[i];
+}
+
+const char *trs_last_error(trs_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+void trs_default_opts(trs_opts *o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->mode = TRS_MODE_PLAIN;
+  o->block = 0;
+  o->nodes_per_thread = 0;
+  o->rounds_per_poll = 0;
+  o->max_rounds = 0;
+  o->threshold = 0.1f;
+  o->persistent = 0;
+  o->trace = 0;
+}
+
+trs_status trs_create(trs_ctx **out, const trs_config *cfg) {
+  if (!out || !cfg) return TRS_E_ARG;
+  *out = nullptr;
+  if (cfg->pool_slots < 2 || cfg->pool_slots > INT32_MAX) return TRS_E_ARG;
+  if (cfg->maxarity < 0 || cfg->maxarity > 5) return TRS_E_ARG;
+  if (cfg->dev_mem && cfg->dev_bytes <= 0) return TRS_E_ARG;
+  trs_ctx *c = new (std::nothrow) trs_ctx();
+  if (!c) return TRS_E_INTERNAL;
+  c->cfg = *cfg;
+  *out = c;
+  return TRS_OK;
+}
+
+void trs_destroy(trs_ctx *c) {
+  if (!c) return;
+  if (c->dev_ready) {
+    (void)hipStreamSynchronize(c->stream);
+    for (void *p : c->owned) (void)hipFree(p);
+    if (c->h_ctl) (void)hipHostFree(c->h_ctl);
+    if (c->h_zero) (void)hipHostFree(c->h_zero);
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    if (c->ev0) (void)hipEventDestroy(c->ev0);
+    if (c->ev1) (void)hipEventDestroy(c->ev1);
+    if (c->own_stream) (void)hipStreamDestroy(c->stream);
+  }
+  delete c;
+}
+
+trs_status trs_load_rules(trs_ctx *c, int32_t n_sym, const int32_t *arity, int32_t n_rules,
+                          const int32_t *rule_off, const int32_t *rule_code, int64_t code_len) {
+  if (!c) return TRS_E_ARG;
+  if (n_sym <= 0 || n_sym > TRS_MAX_SYMBOLS || !arity || n_rules < 0 ||
+      n_rules > TRS_MAX_RULES || (n_rules > 0 && (!rule_off || !rule_code)) || code_len < 0)
+    return c->fail(TRS_E_ARG, "bad sizes or null pointers");
+  c->rules_loaded = c->terms_loaded = c->normalized = false;
+  std::vector<int32_t> ar(arity, arity + n_sym);
+  int maxar = 0;
+  for (int i = 0; i < n_sym; i++) {
+    if (ar[i] < 0 || ar[i] > TRS_MAX_ARITY)
+      return c->fail(TRS_E_RULE, "symbol " + std::to_string(i) + " has an invalid arity");
+    maxar = std::max(maxar, ar[i]);
+  }
+  int A = c->cfg.maxarity ? c->cfg.maxarity : std::max(1, maxar);
+  if (maxar > A)
+    return c->fail(TRS_E_RULE, "a symbol's arity exceeds maxarity " + std::to_string(A));
+  if (A > 5) return c->fail(TRS_E_LIMIT, "maxarity above 5 is not compiled");
+
+  std::vector<std::vector<PNode>> lhs(n_rules);
+  std::vector<std::vector<RNode>> rhs(n_rules);
+  std::vector<uint8_t> has(n_sym, 0);
+  for (int r = 0; r < n_rules; r++) {
+    const std::string rn = "rule " + std::to_string(r) + ": ";
+    int64_t b = rule_off[r], e = rule_off[r + 1];
+    if (b < 0 || e > code_len || e <= b) return c->fail(TRS_E_RULE, rn + "bad offsets");
+    int64_t ll = prefix_len(ar, rule_code, b, e);
+    if (ll < 0) return c->fail(TRS_E_RULE, rn + "malformed left-hand side");
+    int64_t rl = prefix_len(ar, rule_code, b + ll, e);
+    if (rl < 0 || b + ll + rl != e) return c->fail(TRS_E_RULE, rn + "malformed right-hand side");
+    // Definition 1 (1): the left-hand side is not a variable
+    if (rule_code[b] < 0) return c->fail(TRS_E_RULE, rn + "left-hand side is a variable");
+    std::vector<uint8_t> seen(256, 0);
+    for (int64_t i = b; i < b + ll; i++) {
+      if (rule_code[i] < 0) {
+        int v = -1 - rule_code[i];
+        if (v >= 256) return c->fail(TRS_E_LIMIT, rn + "too many variables");
+        // left-linearity: each variable at most once in the left-hand side
+        if (seen[v]) return c->fail(TRS_E_RULE, rn + "left-hand side is not linear");
+        seen[v] = 1;
+      }
+    }
+    for (int64_t i = b + ll; i < e; i++) {
+      if (rule_code[i] < 0) {
+        int v = -1 - rule_code[i];
+        // Definition 1 (2): Var(r) is a subset of Var(l)
+        if (v >= 256 || !seen[v])
+          return c->fail(TRS_E_RULE, rn + "right-hand side variable not in left-hand side");
+      }
+    }
+    parse_lhs(ar, rule_code + b, ll, lhs[r]);
+    parse_rhs(ar, rule_code + b + ll, rl, rhs[r]);
+    has[rule_code[b]] = 1;
+  }
+  // per-symbol grouping in priority order
+  std::vector<std::vector<int>> by_sym(n_sym);
+  for (int r = 0; r < n_rules; r++) by_sym[lhs[r][0].sym].push_back(r);
+  std::vector<int32_t> tab(TAB_SYM + n_sym + n_rules, 0);
+  tab[0] = n_sym;
+  tab[1] = n_rules;
+  tab[2] = A;
+  int first = 0;
+  std::vector<int> order;  // rule ids in grouped order
+  for (int f = 0; f < n_sym; f++) {
+    if (by_sym[f].size() > 255)
+      return c->fail(TRS_E_LIMIT, "more than 255 rules for one symbol");
+    tab[TAB_SYM + f] = tab_sym_word(ar[f], (int)by_sym[f].size(), first);
+    for (int r : by_sym[f]) order.push_back(r);
+    first += (int)by_sym[f].size();
+  }
+  for (size_t i = 0; i < order.size(); i++) {
+    int r = order[i];
+    Program prog;
+    std::string msg;
+    trs_status st = compile_rule(r, ar, has, lhs[r], rhs[r], prog, &msg);
+    if (st != TRS_OK) return c->fail(st, msg);
+    int32_t base = (int32_t)tab.size();
+    tab[TAB_SYM + n_sym + i] = base;
+    for (size_t j = 0; j < prog.words.size(); j++) {
+      int32_t w = prog.words[j];
+      if (j >= 2 && j <= 4) w += base;  // section offsets become absolute
+      tab.push_back(w);
+    }
+  }
+  tab[3] = (int32_t)tab.size();
+  if (tab.size() > TAB_MAX_WORDS) return c->fail(TRS_E_LIMIT, "compiled tables too large");
+  c->n_sym = n_sym;
+  c->n_rules = n_rules;
+  c->arity = ar;
+  c->has_rules = has;
+  c->tab = tab;
+  c->A = A;
+  c->rule_counts.assign(n_rules, 0);
+  c->rules_loaded = true;
+  return TRS_OK;
+}
+
+trs_status trs_load_terms(trs_ctx *c, int32_t n_terms, const int64_t *term_off,
+                          const int32_t *term_code, int64_t code_len) {
+  if (!c) return TRS_E_ARG;
+  if (!c->rules_loaded) return c->fail(TRS_E_STATE, "load rules first");
+  if (n_terms < 0 || (n_terms > 0 && (!term_off || !term_code)) || code_len < 0)
+    return c->fail(TRS_E_ARG, "bad sizes or null pointers");
+  c->terms_loaded = c->normalized = c->cache_valid = false;
+  if (n_terms > 0 && (term_off[0] < 0 || term_off[n_terms] > code_len))
+    return c->fail(TRS_E_ARG, "term offsets out of range");
+  int64_t M = 0;
+  for (int t = 0; t < n_terms; t++) {
+    int64_t b = term_off[t], e = term_off[t + 1];
+    if (e <= b) return c->fail(TRS_E_TERM, "term " + std::to_string(t) + " is empty");
+    for (int64_t i = b; i < e; i++)
+      if (term_code[i] < 0 || term_code[i] >= c->n_sym)
+        return c->fail(TRS_E_TERM, "term " + std::to_string(t) + " is not ground / bad symbol");
+    if (prefix_len(c->arity, term_code, b, e) != e - b)
+      return c->fail(TRS_E_TERM, "term " + std::to_string(t) + " is malformed");
+    M += e - b;
+  }
+  if (M + 1 > c->cfg.pool_slots)
+    return c->fail(TRS_E_POOL, "initial terms need " + std::to_string(M + 1) + " slots");
+  const int A = c->A;
+  c->n_init = M + 1;
+  c->img_hss.assign(M + 1, 0);
+  c->img_args.assign((size_t)(M + 1) * A, 0);
+  c->img_rc.assign(M + 1, 0);
+  c->img_state.assign(M + 1, ST_FREE);
+  c->roots.assign(n_terms, 0);
+  int64_t slot = 1;
+  std::vector<std::pair<int64_t, int>> st;  // (parent slot, next arg)
+  for (int t = 0; t < n_terms; t++) {
+    int64_t b = term_off[t], e = term_off[t + 1];
+    int64_t first = slot;
+    c->roots[t] = (int32_t)first;
+    st.clear();
+    for (int64_t i = b; i < e; i++) {
+      int32_t s = term_code[i];
+      int64_t me = slot++;
+      c->img_hss[me] = s;
+      c->img_rc[me] = 1;  // one parent, or the root-table entry
+      if (!st.empty()) {
+        c->img_args[(size_t)st.back().first * A + st.back().second] = (int32_t)me;
+        st.back().second++;
+      }
+      if (c->arity[s] > 0) st.push_back({me, 0});
+      while (!st.empty() && st.back().second == c->arity[c->img_hss[st.back().first]]) st.pop_back();
+    }
+    // constructor-only subterms are normal forms from the start: a node whose
+    // symbol has no rules and whose arguments are all normal forms
+    for (int64_t me = slot - 1; me >= first; me--) {
+      int32_t s = c->img_hss[me];
+      bool nf = !c->has_rules[s];
+      for (int j = 0; j < c->arity[s] && nf; j++)
+        nf = c->img_state[c->img_args[(size_t)me * A + j]] == ST_NF;
+      c->img_state[me] = nf ? (uint8_t)ST_NF : (uint8_t)ST_ACTIVE;
+    }
+  }
+  c->n_terms = n_terms;
+  c->terms_loaded = true;
+  return TRS_OK;
+}
+
+trs_status trs_normalize(trs_ctx *c, const trs_opts *opts_in, trs_stats *stats) {
+  if (!c) return TRS_E_ARG;
+  if (!c->terms_loaded) return c->fail(TRS_E_STATE, "load rules and terms first");
+  trs_opts o;
+  if (opts_in)
+    o = *opts_in;
+  else
+    trs_default_opts(&o);
+  if (o.mode != TRS_MODE_PLAIN) return c->fail(TRS_E_ARG, "mode not available");
+  const int B = o.block ? o.block : default_block();
+  const int npt = o.nodes_per_thread ? o.nodes_per_thread : default_npt();
+  if (B < 64 || B > 1024 || (B & 63)) return c->fail(TRS_E_ARG, "block must be 64..1024, /64");
+  if (!(npt == 1 || npt == 2 || npt == 4 || npt == 8 || npt == 16))
+    return c->fail(TRS_E_ARG, "nodes_per_thread must be 1, 2, 4, 8 or 16");
+  if (B * npt > 16384) return c->fail(TRS_E_ARG, "block * nodes_per_thread above 16384");
+  if (o.max_rounds < 0 || o.rounds_per_poll < 0) return c->fail(TRS_E_ARG, "negative limits");
+  trs_status st = device_init(c);
+  if (st != TRS_OK) return st;
+  c->normalized = false;
+  c->cache_valid = false;
+  const int A = c->A;
+  const int64_t M1 = c->n_init;
+  hipStream_t s = c->stream;
+  HIPCHK(c, hipMemcpyAsync(c->pool.hss, c->img_hss.data(), M1 * 4, hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(c->pool.args, c->img_args.data(), M1 * A * 4, hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(c->pool.rc, c->img_rc.data(), M1 * 4, hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(c->pool.state, c->img_state.data(), M1, hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(c->d_tab, c->tab.data(), c->tab.size() * 4, hipMemcpyHostToDevice, s));
+  std::memset(c->h_ctl, 0, sizeof(Ctl));
+  c->h_ctl->n[0] = (int32_t)M1;
+  c->h_ctl->peak_n = (int32_t)M1;
+  HIPCHK(c, hipMemcpyAsync(c->d_ctl, c->h_ctl, sizeof(Ctl), hipMemcpyHostToDevice, s));
+  unsigned long long zero = 0;
+  HIPCHK(c, hipMemcpyAsync(c->d_bar, &zero, sizeof(zero), hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+
+  RoundArgs ra{};
+  ra.p = c->pool;
+  ra.ctl = c->d_ctl;
+  ra.tab = c->d_tab;
+  ra.tab_words = (int32_t)c->tab.size();
+  ra.n_sym = c->n_sym;
+  ra.n_rules = c->n_rules;
+  ra.npt = npt;
+  ra.bar = c->d_bar;
+  const size_t lds = trs_round_lds_bytes(B, npt, ra.tab_words, c->n_rules);
+  if (lds > 160 * 1024) return c->fail(TRS_E_ARG, "configuration needs too much LDS");
+  const int TILE = B * npt;
+  HIPCHK(c, trs_prepare_kernels(A, lds));
+  int gmax = 8 * c->cu_count;
+  if (o.persistent) {
+    gmax = trs_max_resident(A, B, lds, c->cfg.device);
+    if (gmax <= 0) return c->fail(TRS_E_HIP, "persistent kernel cannot be resident");
+  }
+  // grid sizes are powers of two (at least 8 when large enough) so that the
+  // captured chunk is re-captured only when the slot extent doubles
+  auto grid_for = [&](int64_t n) {
+    int64_t need = std::max<int64_t>(1, (n + TILE - 1) / TILE);
+    int64_t g = 1;
+    while (g < need) g <<= 1;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(g, gmax));
+  };
+  int64_t r = 0, n_est = M1, launches = 0;
+  const int K = o.persistent ? 0 : 64;   // rounds per captured chunk
+  int P = 1;                             // chunks (or persistent launches) per poll
+  int KP = o.rounds_per_poll ? o.rounds_per_poll : 64;  // persistent rounds per launch
+  HIPCHK(c, hipEventRecord(c->ev0, s));
+  const size_t small = offsetof(Ctl, cnt);
+  trs_status result = TRS_OK;
+  for (;;) {
+    const int g = grid_for(n_est);
+    if (o.persistent) {
+      for (int i = 0; i < P; i++) {
+        int64_t k_here = KP;
+        if (o.max_rounds > 0) k_here = std::min<int64_t>(k_here, o.max_rounds + 1 - r);
+        if (k_here <= 0) break;
+        HIPCHK(c, hipMemcpyAsync(c->d_bar, c->h_zero, 8, hipMemcpyHostToDevice, s));
+        ra.r0 = (int32_t)r;
+        ra.nrounds = (int32_t)k_here;
+        HIPCHK(c, trs_launch_persistent(A, ra, g, B, s));
+        launches++;
+        r += k_here;
+      }
+    } else {
+      if (!c->gexec || c->g_grid != g || c->g_block != B || c->g_npt != npt || c->g_k != K ||
+          c->g_lds != lds) {
+        if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+        if (c->graph) (void)hipGraphDestroy(c->graph);
+        c->gexec = nullptr;
+        c->graph = nullptr;
+        HIPCHK(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        for (int k = 0; k < K; k++) {
+          ra.r0 = k;
+          hipError_t e = trs_launch_round(A, ra, g, B, s);
+          if (e != hipSuccess) {
+            hipGraph_t junk;
+            (void)hipStreamEndCapture(s, &junk);
+            return c->fail(TRS_E_HIP, std::string("capture: ") + hipGetErrorString(e));
+          }
+        }
+        HIPCHK(c, trs_launch_advance(c->d_ctl, K, s));
+        HIPCHK(c, hipStreamEndCapture(s, &c->graph));
+        HIPCHK(c, hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
+        c->g_grid = g;
+        c->g_block = B;
+        c->g_npt = npt;
+        c->g_k = K;
+        c->g_lds = lds;
+      }
+      for (int i = 0; i < P; i++) {
+        HIPCHK(c, hipGraphLaunch(c->gexec, s));
+        launches += K;
+        r += K;
+        if (o.max_rounds > 0 && r > o.max_rounds) break;
+      }
+    }
+    HIPCHK(c, hipMemcpyAsync(c->h_ctl, c->d_ctl, small, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    if (c->h_ctl->abort) {
+      result = c->fail(TRS_E_INTERNAL, "device-wide barrier timed out");
+      break;
+    }
+    if (c->h_ctl->done) break;
+    if (o.max_rounds > 0 && r > o.max_rounds) {
+      result = c->fail(TRS_E_ROUNDS, "no normal form within max_rounds");
+      break;
+    }
+    // the extent at the start of the last issued round
+    n_est = std::max<int64_t>(n_est, c->h_ctl->peak_n);
+    P = std::min(P * 2, o.rounds_per_poll ? 1 : 64);
+  }
+  HIPCHK(c, hipEventRecord(c->ev1, s));
+  HIPCHK(c, hipMemcpyAsync(c->h_ctl, c->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  float ms = 0.f;
+  HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+  const Ctl &h = *c->h_ctl;
+  if (result == TRS_OK && h.err) {
+    result = c->fail(h.err, h.err == TRS_E_POOL ? "node pool exhausted during rewriting"
+                                                : "device reported an inconsistency");
+  }
+  for (int i = 0; i < c->n_rules; i++) {
+    unsigned long long t = 0;
+    for (int j = 0; j < 4; j++) t += h.rule_apps[i][j];
+    c->rule_counts[i] = (int64_t)t;
+  }
+  if (stats) {
+    std::memset(stats, 0, sizeof(*stats));
+    auto sum = [&](int k) {
+      unsigned long long t = 0;
+      for (int j = 0; j < CTL_SPREAD; j++) t += h.stat[k][j];
+      return (int64_t)t;
+    };
+    stats->rounds = h.done ? h.done_round : r;
+    for (int64_t v : c->rule_counts) stats->rule_apps += v;
+    stats->node_visits = sum(STAT_VISITS);
+    stats->active_visits = sum(STAT_ACTIVE);
+    stats->allocs = sum(STAT_ALLOC);
+    stats->frees = sum(STAT_FREED);
+    stats->peak_slots = h.peak_n;
+    stats->gc_rounds = h.gc_rounds;
+    stats->mlp_evals = sum(STAT_MLP);
+    stats->full_sweeps = 0;
+    stats->launches = launches;
+    stats->device_ms = ms;
+  }
+  if (result != TRS_OK) return result;
+  c->n_final = h.n_final;
+  c->normalized = true;
+  return TRS_OK;
+}
+
+trs_status trs_read_nf(trs_ctx *c, int32_t term_id, int32_t *buf, int64_t cap, int64_t *len_out) {
+  if (!c || !len_out) return TRS_E_ARG;
+  if (!c->normalized) return c->fail(TRS_E_STATE, "normalize first");
+  if (term_id < 0 || term_id >= c->n_terms) return c->fail(TRS_E_ARG, "bad term id");
+  const int A = c->A;
+  if (!c->cache_valid) {
+    const int64_t n = c->n_final;
+    c->c_hss.resize(n);
+    c->c_args.resize((size_t)n * A);
+    c->c_state.resize(n);
+    HIPCHK(c, hipMemcpy(c->c_hss.data(), c->pool.hss, n * 4, hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(c->c_args.data(), c->pool.args, n * A * 4, hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(c->c_state.data(), c->pool.state, n, hipMemcpyDeviceToHost));
+    c->cache_valid = true;
+  }
+  const int64_t n = c->n_final;
+  std::vector<int32_t> stk;
+  stk.push_back(c->roots[term_id]);
+  int64_t len = 0;
+  while (!stk.empty()) {
+    int32_t x = stk.back();
+    stk.pop_back();
+    if (x <= 0 || x >= n) return c->fail(TRS_E_INTERNAL, "dangling argument index");
+    if (!(c->c_state[x] & ST_NF)) return c->fail(TRS_E_INTERNAL, "reachable node not in normal form");
+    int32_t s = c->c_hss[x];
+    if (s < 0 || s >= c->n_sym) return c->fail(TRS_E_INTERNAL, "bad symbol in pool");
+    if (buf) {
+      if (len >= cap) return c->fail(TRS_E_ARG, "buffer too small");
+      buf[len] = s;
+    }
+    len++;
+    if (len > INT32_MAX) return c->fail(TRS_E_LIMIT, "normal form too long");
+    for (int j = c->arity[s] - 1; j >= 0; j--) stk.push_back(c->c_args[(size_t)x * A + j]);
+  }
+  *len_out = len;
+  return TRS_OK;
+}
+
+trs_status trs_rule_counts(trs_ctx *c, int64_t *out, int32_t cap) {
+  if (!c || !out) return TRS_E_ARG;
+  if (!c->normalized) return c->fail(TRS_E_STATE, "normalize first");
+  if (cap < c->n_rules) return c->fail(TRS_E_ARG, "buffer too small");
+  for (int i = 0; i < c->n_rules; i++) out[i] = c->rule_counts[i];
+  return TRS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,111 @@
+// trs_layout.h -- device data layout shared by the library's host runtime and
+// its HIP kernels (not part of the public ABI).
+//
+// Node pool: structure of arrays indexed by slot (Section 3's arrays):
+//   hss[N]      int32  head symbol of the term stored at the slot
+//   args[N*A]   int32  argument slots, maxarity-strided (slot s owns
+//                      args[s*A .. s*A+A)); entries past the arity of hss[s]
+//                      are unspecified.  Slot 0 is never used, as in the paper.
+//   state[N]    uint8  replaces the paper's nf / nf_read pair (see below)
+//   rc[N]       int32  reference count (the paper's refcounts)
+//   fstack[2][N] int32 two free-index stacks (the paper's free_indices); round
+//                      r pops stack r&1 and pushes stack (r+1)&1
+//   dead[2][N]  int32  nodes whose count reached zero in round r go to list
+//                      r&1 and are collected in round r+1
+//
+// State byte.  A node that becomes a normal form, or is created, in round r
+// must not be seen as such by other nodes until round r+1 (the paper keeps a
+// read copy nf_read of nf for this, Section 3).  Instead of copying, the
+// marker carries the parity of the round that set it:
+//   0x00          free (or never used)
+//   0x01          live, not in normal form           (ACTIVE)
+//   0x03 | e<<2   live, created in a round of parity e (ACTIVE|PEND)
+//   0x80          live, normal form                  (NF)
+//   0x82 | e<<2   live, became normal form in a round of parity e (NF|PEND)
+// A marker with the current parity is "not yet"; with the other parity it is
+// already valid, and the slot's own sweep rewrites it to the plain state in
+// the next round, so markers never outlive two rounds.
+#pragma once
+#include <stdint.h>
+
+#define ST_FREE 0x00u
+#define ST_ACTIVE 0x01u
+#define ST_PEND 0x02u
+#define ST_EPOCH 0x04u
+#define ST_NF 0x80u
+
+// ---------------------------------------------------------------- tables
+// Compiled rule tables (int32 words), loaded into LDS by every workgroup.
+//   [0] n_sym  [1] n_rules  [2] A  [3] total words
+//   [TAB_SYM + f]                       symbol word: arity | nrules<<8 | first<<16
+//   [TAB_SYM + n_sym + r]               word offset of rule r's program
+// Rule program at offset p:
+//   p+0  npat | nnew<<4 | var_root<<8 | root_nf<<9 | npos<<12 | nneg<<16 | rootpat<<20
+//   p+1  root symbol (non-variable right-hand side) or -1
+//   p+2  offset of the root operand list      (ar(root) operand words)
+//   p+3  offset of the new-node list          (per node: header, operands)
+//   p+4  offset of the reference-count deltas (npos positive, then nneg negative)
+//   p+5  rule index (textual order, for the per-rule counters)
+//   p+6 .. p+5+npat   pattern nodes 1..npat in prefix order:
+//                     parent | pos<<4 | is_var<<8 | sym<<16
+// Operand word: k >= 0 -> the slot matched by pattern node k (k >= 1);
+//               k <  0 -> the slot of new node (-1-k).
+// New-node header: sym | rc_init<<16 | born_nf<<24.
+// Delta word: pattern node | (delta & 0xff)<<8 (signed 8-bit delta).
+#define TAB_SYM 4
+#define TAB_MAX_WORDS 4096
+
+static inline int32_t tab_sym_word(int32_t arity, int32_t nrules, int32_t first) {
+  return arity | (nrules << 8) | (first << 16);
+}
+
+// ---------------------------------------------------------------- control
+#define CTL_SPREAD 64    // statistics counters are spread over this many words
+#define CTL_NSTAT 8
+enum {
+  STAT_ACTIVE = 0,  // live non-normal-form slots visited
+  STAT_READY,       // of those, all arguments in normal form
+  STAT_FIRED,       // rule applications
+  STAT_NFSET,       // became normal form without a rule (no match / no rules)
+  STAT_ALLOC,       // nodes created
+  STAT_FREED,       // nodes collected
+  STAT_VISITS,      // slots examined
+  STAT_MLP,         // predictor evaluations
+};
+
+struct RoundCnt {
+  int32_t alloc;   // allocation claims in the round
+  int32_t push;    // free-stack pushes in the round
+  int32_t dead;    // dead-list appends in the round
+  int32_t active;  // nonzero if a live non-normal-form slot was seen
+  int32_t err;     // nonzero: trs_status of a device-detected error
+  int32_t front;   // frontier appends (frontier modes)
+  int32_t pad[2];
+};
+
+struct Ctl {
+  int32_t done;        // set once the fixpoint (and collection) is reached
+  int32_t done_round;  // number of rounds executed
+  int32_t err;         // copied from the round counters when done
+  int32_t n_final;     // slot extent at the end
+  int32_t n[3];        // slot extent n at the start of round r (index r % 3)
+  int32_t fs[3][2];    // free-stack sizes at the start of round r
+  int32_t peak_n;
+  int32_t gc_rounds;
+  int32_t r_base;      // round number of chunk offset 0 (advanced by the graph)
+  int32_t abort;       // set when a device-wide barrier wait timed out
+  int32_t pad[2];
+  RoundCnt cnt[3];     // counters accumulated during round r (index r % 3)
+  unsigned long long stat[CTL_NSTAT][CTL_SPREAD];
+  unsigned long long rule_apps[256][4];
+};
+
+struct Pool {
+  int32_t *hss;
+  int32_t *args;
+  uint8_t *state;
+  int32_t *rc;
+  int32_t *fstack0, *fstack1;
+  int32_t *dead0, *dead1;
+  int64_t N;
+};

@@ -1,0 +1,277 @@
+"""Python binding of libtrs (include/trs.h): argument marshalling only.
+
+Every step of the rewriting runs in the HIP library; this module converts
+numpy arrays to pointers, passes PyTorch's device memory and stream to the
+library, and turns status codes into exceptions.  The functions carry the C
+names (``trs_create``, ``trs_load_rules``, ``trs_load_terms``,
+``trs_normalize``, ``trs_read_nf`` ...); :class:`Context` wraps them.
+
+The library must have been built (``python -m paper_2009_07174_amd.build``);
+importing this module without it raises ``ImportError`` -- there is no other
+implementation to fall back to.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtrs.so")
+
+TRS_OK, TRS_E_ARG, TRS_E_STATE, TRS_E_RULE, TRS_E_TERM = 0, -1, -2, -3, -4
+TRS_E_POOL, TRS_E_ROUNDS, TRS_E_HIP, TRS_E_LIMIT, TRS_E_INTERNAL = -5, -6, -7, -8, -9
+TRS_MODE_PLAIN, TRS_MODE_FRONTIER, TRS_MODE_LEARNED = 0, 1, 2
+
+
+class trs_config(ctypes.Structure):
+    _fields_ = [("pool_slots", ctypes.c_int64), ("maxarity", ctypes.c_int32),
+                ("device", ctypes.c_int32), ("hip_stream", ctypes.c_void_p),
+                ("dev_mem", ctypes.c_void_p), ("dev_bytes", ctypes.c_int64)]
+
+
+class trs_opts(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("block", ctypes.c_int32),
+                ("nodes_per_thread", ctypes.c_int32), ("rounds_per_poll", ctypes.c_int32),
+                ("max_rounds", ctypes.c_int64), ("threshold", ctypes.c_float),
+                ("persistent", ctypes.c_int32), ("trace", ctypes.c_int32)]
+
+
+class trs_stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in (
+        "rounds", "rule_apps", "node_visits", "active_visits", "allocs", "frees",
+        "peak_slots", "gc_rounds", "mlp_evals", "full_sweeps", "launches")] + [
+        ("device_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+EXPORTS = ["trs_create", "trs_destroy", "trs_load_rules", "trs_load_terms", "trs_normalize",
+           "trs_read_nf", "trs_rule_counts", "trs_default_opts", "trs_device_bytes",
+           "trs_status_str", "trs_last_error"]
+
+
+def _load_lib():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_2009_07174_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    vp = ctypes.c_void_p
+    i32p, i64p = P(ctypes.c_int32), P(ctypes.c_int64)
+    lib.trs_create.argtypes = [P(vp), P(trs_config)]
+    lib.trs_create.restype = ctypes.c_int32
+    lib.trs_destroy.argtypes = [vp]
+    lib.trs_destroy.restype = None
+    lib.trs_load_rules.argtypes = [vp, ctypes.c_int32, i32p, ctypes.c_int32, i32p, i32p,
+                                   ctypes.c_int64]
+    lib.trs_load_rules.restype = ctypes.c_int32
+    lib.trs_load_terms.argtypes = [vp, ctypes.c_int32, i64p, i32p, ctypes.c_int64]
+    lib.trs_load_terms.restype = ctypes.c_int32
+    lib.trs_normalize.argtypes = [vp, P(trs_opts), P(trs_stats)]
+    lib.trs_normalize.restype = ctypes.c_int32
+    lib.trs_read_nf.argtypes = [vp, ctypes.c_int32, i32p, ctypes.c_int64, i64p]
+    lib.trs_read_nf.restype = ctypes.c_int32
+    lib.trs_rule_counts.argtypes = [vp, i64p, ctypes.c_int32]
+    lib.trs_rule_counts.restype = ctypes.c_int32
+    lib.trs_default_opts.argtypes = [P(trs_opts)]
+    lib.trs_default_opts.restype = None
+    lib.trs_device_bytes.argtypes = [ctypes.c_int64, ctypes.c_int32]
+    lib.trs_device_bytes.restype = ctypes.c_int64
+    lib.trs_status_str.argtypes = [ctypes.c_int32]
+    lib.trs_status_str.restype = ctypes.c_char_p
+    lib.trs_last_error.argtypes = [vp]
+    lib.trs_last_error.restype = ctypes.c_char_p
+    return lib
+
+
+_lib = _load_lib()
+
+
+class TRSError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_lib.trs_status_str(code).decode()} ({code}): {msg}")
+        self.code = code
+
+
+def _i32(a):
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+def _i64(a):
+    a = np.ascontiguousarray(a, dtype=np.int64)
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+
+
+# ----------------------------------------------------------- C-named calls
+
+def trs_create(cfg: trs_config):
+    h = ctypes.c_void_p()
+    st = _lib.trs_create(ctypes.byref(h), ctypes.byref(cfg))
+    if st != TRS_OK:
+        raise TRSError(st, "trs_create")
+    return h
+
+
+def trs_destroy(h):
+    _lib.trs_destroy(h)
+
+
+def _check(h, st):
+    if st != TRS_OK:
+        raise TRSError(st, _lib.trs_last_error(h).decode())
+
+
+def trs_load_rules(h, arity, rule_off, rule_code):
+    a, ap = _i32(arity)
+    o, op = _i32(rule_off)
+    c, cp = _i32(rule_code)
+    _check(h, _lib.trs_load_rules(h, len(a), ap, len(o) - 1, op, cp, len(c)))
+
+
+def trs_load_terms(h, term_off, term_code):
+    o, op = _i64(term_off)
+    c, cp = _i32(term_code)
+    _check(h, _lib.trs_load_terms(h, len(o) - 1, op, cp, len(c)))
+
+
+def trs_default_opts() -> trs_opts:
+    o = trs_opts()
+    _lib.trs_default_opts(ctypes.byref(o))
+    return o
+
+
+def trs_normalize(h, opts: trs_opts) -> dict:
+    st = trs_stats()
+    _check(h, _lib.trs_normalize(h, ctypes.byref(opts), ctypes.byref(st)))
+    return st.as_dict()
+
+
+def trs_read_nf(h, term_id: int) -> np.ndarray:
+    n = ctypes.c_int64(0)
+    _check(h, _lib.trs_read_nf(h, term_id, None, 0, ctypes.byref(n)))
+    out = np.empty(n.value, dtype=np.int32)
+    _check(h, _lib.trs_read_nf(h, term_id, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                               len(out), ctypes.byref(n)))
+    return out
+
+
+def trs_rule_counts(h, n_rules: int) -> np.ndarray:
+    out = np.zeros(max(n_rules, 1), dtype=np.int64)
+    _check(h, _lib.trs_rule_counts(h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                   len(out)))
+    return out[:n_rules]
+
+
+def trs_device_bytes(pool_slots: int, maxarity: int) -> int:
+    return int(_lib.trs_device_bytes(pool_slots, maxarity))
+
+
+# ----------------------------------------------------------- convenience
+
+@dataclass
+class Options:
+    mode: int = TRS_MODE_PLAIN
+    block: int = 0
+    nodes_per_thread: int = 0
+    rounds_per_poll: int = 0
+    max_rounds: int = 0
+    threshold: float = 0.1
+    persistent: int = 0
+    trace: int = 0
+
+    def to_c(self) -> trs_opts:
+        o = trs_default_opts()
+        for k in ("mode", "block", "nodes_per_thread", "rounds_per_poll", "max_rounds",
+                  "threshold", "persistent", "trace"):
+            setattr(o, k, getattr(self, k))
+        return o
+
+
+class Context:
+    """One rewriting context.  With ``torch_memory=True`` (and a GPU present)
+    the device block is a PyTorch allocation and the work is issued on
+    PyTorch's current stream; otherwise the library allocates and creates its
+    own stream."""
+
+    def __init__(self, pool_slots: int, maxarity: int = 0, device: int = 0,
+                 torch_memory: bool = True, stream=None):
+        # the C context is created by load_rules, once the argument stride
+        # (maxarity, or the highest arity of the system) is known
+        self.pool_slots, self.maxarity, self.device = pool_slots, maxarity, device
+        self.torch_memory, self.stream = torch_memory, stream
+        self.h = None
+        self._keep = None
+        self.stream_handle = None
+        self.n_rules = 0
+
+    def _create(self, A: int):
+        self.close()
+        cfg = trs_config(pool_slots=self.pool_slots, maxarity=A, device=self.device)
+        if self.torch_memory:
+            import torch
+            if torch.cuda.is_available():
+                nbytes = trs_device_bytes(self.pool_slots, A)
+                if nbytes < 0:
+                    raise TRSError(TRS_E_ARG, "bad pool size or maxarity")
+                dev = torch.device("cuda", self.device)
+                self._keep = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+                s = self.stream if self.stream is not None else torch.cuda.current_stream(dev)
+                self._stream = s
+                self.stream_handle = s.cuda_stream
+                cfg.dev_mem = self._keep.data_ptr()
+                cfg.dev_bytes = nbytes
+                cfg.hip_stream = self.stream_handle
+        self.h = trs_create(cfg)
+
+    def close(self):
+        if getattr(self, "h", None):
+            trs_destroy(self.h)
+            self.h = None
+        self._keep = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def load_rules(self, arity, rule_off, rule_code):
+        arity = np.asarray(arity)
+        A = self.maxarity or max(1, int(arity.max()) if len(arity) else 1)
+        self._create(A)
+        trs_load_rules(self.h, arity, rule_off, rule_code)
+        self.n_rules = len(rule_off) - 1
+
+    def load_trs(self, trs):
+        self.load_rules(*trs.encode_rules())
+
+    def load_terms(self, term_off, term_code):
+        trs_load_terms(self.h, term_off, term_code)
+
+    def load_term_list(self, terms):
+        off = np.zeros(len(terms) + 1, dtype=np.int64)
+        off[1:] = np.cumsum([len(t) for t in terms])
+        code = np.concatenate(terms) if terms else np.zeros(0, np.int32)
+        self.load_terms(off, code)
+
+    def normalize(self, opts: Options | None = None, **kw) -> dict:
+        o = opts or Options(**kw)
+        return trs_normalize(self.h, o.to_c())
+
+    def read_nf(self, term_id: int) -> np.ndarray:
+        return trs_read_nf(self.h, term_id)
+
+    def rule_counts(self) -> np.ndarray:
+        return trs_rule_counts(self.h, self.n_rules)

@@ -1,0 +1,149 @@
+"""GPU parity: the HIP path (through the C-ABI) against the oracle.
+
+Normal forms must be byte-identical canonical serialisations and the rule
+applications, per rule, must be equal (the innermost rewrites are the same
+whatever the schedule when no right-hand side duplicates a subterm that is
+not yet a normal form, which holds for every system used here).
+"""
+
+import glob
+import os
+
+import numpy as np
+import pytest
+
+from trs_workloads import generators as G
+from trs_workloads import parse_trs, systems
+from tests import closed_forms as CF
+from tests.gpu_util import assert_parity, run_gpu, say
+from tests.test_oracle_pins import load_fixture
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.mark.parametrize("path", sorted(glob.glob(os.path.join(GOLDEN, "*.trs"))),
+                         ids=lambda p: os.path.basename(p))
+def test_golden(path):
+    trs, ex = load_fixture(path)
+    assert_parity(trs, [trs.encode(ex["input"])], 1 << 12, label=os.path.basename(path))
+
+
+def test_peano_small_trees():
+    trs = systems.peano()
+    rng = np.random.default_rng(11)
+    terms = [G.peano_tree(trs, rng, int(rng.integers(1, 300))) for _ in range(24)]
+    assert_parity(trs, terms, 1 << 18, label="peano small")
+
+
+def test_cfg0():
+    w = G.cfg0()
+    st = assert_parity(w.trs, w.terms, w.pool_slots, w.maxarity, label=w.name)
+    v, cnt = CF.peano_eval(w.trs, w.terms[0])
+    assert st["rule_apps"] == sum(cnt.values())
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 3, 7, 12, 16])
+def test_fib_small(n):
+    trs = systems.fib()
+    assert_parity(trs, [G.g_term(trs, n)], 1 << 16, label=f"g({n})")
+
+
+@pytest.mark.parametrize("n", [20, 25])
+def test_cfg1(n):
+    w = G.cfg1(n)
+    st = assert_parity(w.trs, w.terms, w.pool_slots, w.maxarity, label=w.name)
+    assert st["rule_apps"] == sum(CF.g_counts(n).values())
+
+
+def test_msort_small_lists():
+    trs = systems.msort()
+    rng = np.random.default_rng(12)
+    terms = [G.sort_term(trs, rng.integers(0, 64, size=int(rng.integers(0, 70))))
+             for _ in range(16)]
+    assert_parity(trs, terms, 1 << 20, label="msort small")
+
+
+def test_cfg2():
+    w = G.cfg2()
+    assert_parity(w.trs, w.terms, w.pool_slots, w.maxarity, label=w.name)
+
+
+def test_batch_mini():
+    w = G.cfg3(n_terms=96, pool_slots=1 << 22, scale="mini")
+    assert_parity(w.trs, w.terms, w.pool_slots, w.maxarity, label=w.name)
+
+
+@pytest.mark.parametrize("block,npt", [(64, 1), (128, 2), (256, 4), (512, 8), (1024, 16)])
+def test_launch_shapes_agree(block, npt):
+    w = G.cfg3(n_terms=48, pool_slots=1 << 21, scale="mini")
+    assert_parity(w.trs, w.terms, w.pool_slots, w.maxarity, label=f"mini B{block} npt{npt}",
+                  block=block, nodes_per_thread=npt)
+
+
+def test_ttree():
+    w = G.ttree(10, pool_slots=1 << 18)
+    st = assert_parity(w.trs, w.terms, w.pool_slots, w.maxarity, label=w.name)
+    assert st["rule_apps"] == CF.ttree_counts(10)
+
+
+def test_msort5_arity5():
+    trs = systems.msort5()
+    rng = np.random.default_rng(5)
+
+    def lst(vs):
+        s = "Nil"
+        for v in reversed(vs):
+            s = f"Cons({'S(' * int(v)}Zero{')' * int(v)}, {s})"
+        return s
+    terms = []
+    for _ in range(6):
+        leaves = [f"Leaf(Sort({lst(rng.integers(0, 9, size=7))}))" for _ in range(4)]
+        terms.append(trs.encode(f"Node(Node({leaves[0]}, {leaves[1]}), Node({leaves[2]}, {leaves[3]}))"))
+    assert_parity(trs, terms, 1 << 16, label="msort5")
+
+
+def test_already_normal_and_empty():
+    trs = systems.peano()
+    nfs, counts, st = run_gpu(trs, [trs.encode("S(S(0))"), trs.encode("0")], 1 << 10)
+    assert [list(x) for x in nfs] == [list(trs.encode("S(S(0))")), [0]]
+    assert counts.sum() == 0
+    nfs, counts, st = run_gpu(trs, [], 1 << 10)
+    assert nfs == [] and counts.sum() == 0
+
+
+def test_pool_exhaustion_reports_error():
+    from paper_2009_07174_amd import trs as T
+    trs = systems.fib()
+    with pytest.raises(T.TRSError) as e:
+        run_gpu(trs, [G.g_term(trs, 14)], 256)
+    assert e.value.code == T.TRS_E_POOL
+
+
+def test_round_limit_reports_error():
+    from paper_2009_07174_amd import trs as T
+    trs = parse_trs(systems.LOOP)
+    with pytest.raises(T.TRSError) as e:
+        run_gpu(trs, [trs.encode("f(a)")], 1 << 16, max_rounds=200)
+    assert e.value.code in (T.TRS_E_ROUNDS, T.TRS_E_POOL)
+
+
+def test_persistent_kernel_agrees():
+    w = G.cfg3(n_terms=48, pool_slots=1 << 21, scale="mini")
+    assert_parity(w.trs, w.terms, w.pool_slots, w.maxarity, label="mini persistent",
+                  persistent=1)
+
+
+def test_repeat_normalize_same_context():
+    from paper_2009_07174_amd import trs as T
+    trs = systems.fib()
+    ctx = T.Context(1 << 16, 0)
+    try:
+        ctx.load_trs(trs)
+        for n in (9, 13, 9):
+            ctx.load_term_list([G.g_term(trs, n)])
+            ctx.normalize()
+            np.testing.assert_array_equal(ctx.read_nf(0), CF.numeral_code(trs, CF.fib(n + 1)))
+    finally:
+        ctx.close()
