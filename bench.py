@@ -1,0 +1,211 @@
+#!/usr/bin/env python3
+"""Benchmark of the round-synchronous innermost rewriter on one MI355X.
+
+One step = one ``trs_normalize`` of the whole workload: the pool is restored
+on the device from the resident initial image (no host transfer), then the
+rounds run until the fixpoint.  ``value`` is rule applications per second of
+the whole job (the paper's "rewritten terms per second"), with the inputs
+already in HBM when the timed region starts.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cfg3]
+                       [--mode plain|persistent] [--no-cpu-baseline]
+
+The default workload is the batched configuration: 4096 independent terms
+(plus/times trees, g(S^n(0)) and merge sorts in equal parts) in one 2^27-slot
+pool, whose full sweeps exceed the 256 MB Infinity Cache.  The printed JSON
+line carries a ``roofline`` object for the round kernel (algorithmic bytes of
+the run / device time of the round loop, against 8 TB/s) and a
+``cpu_baseline`` object: the CPU oracle timed on a bounded sample of the same
+workload on one host core.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_workload(name: str):
+    from trs_workloads import generators as G
+    if name == "cfg0":
+        return G.cfg0()
+    if name.startswith("cfg1"):
+        n = int(name.split("_")[1]) if "_" in name else 25
+        return G.cfg1(n)
+    if name == "cfg2":
+        return G.cfg2()
+    if name == "cfg3":
+        return G.cfg3()
+    if name == "cfg4":
+        return G.cfg4()
+    if name.startswith("ttree"):
+        d = int(name.split("_")[1]) if "_" in name else 22
+        return G.ttree(d)
+    raise SystemExit(f"unknown workload {name}")
+
+
+def algorithmic_bytes(st: dict, A: int) -> dict:
+    """Bytes the method itself must move, from the run's counters:
+    1 B state per visited slot; per live non-normal-form slot still blocked
+    by the argument recorded at its previous examination 4 B (that argument
+    index) + 1 B (its state); per other live non-normal-form slot 4 B symbol,
+    4A B argument indices and A one-byte argument-state gathers; per ready
+    slot A 4-byte argument-symbol gathers for matching; per rule application
+    the rewritten root (4 + 4A + 1 B); per created node 4 + 4A + 4 + 1 B; per
+    reference-count atomic 8 B (read and write of a 4-byte count); per
+    collected node its symbol, arguments, state and free-list entry."""
+    parts = {
+        "sweep": st["node_visits"] * 1,
+        "memo_blocked": st["memo_blocked"] * (4 + 1),
+        "active": (st["active_visits"] - st["memo_blocked"]) * (4 + 4 * A + A),
+        "match": st["ready_visits"] * 4 * A,
+        "rewrite": st["rule_apps"] * (4 + 4 * A + 1),
+        "alloc": st["allocs"] * (4 + 4 * A + 4 + 1),
+        "rc_atomics": st["rc_atomics"] * 8,
+        "collect": st["frees"] * (4 + 4 * A + 1 + 4),
+    }
+    parts["total"] = sum(parts.values())
+    return parts
+
+
+def cpu_baseline(w, budget_s: float = 15.0):
+    """The oracle, as it stands, on a bounded sample of the same workload:
+    terms in a fixed seeded order until about budget_s of normalisation time
+    has accumulated (one host core)."""
+    import numpy as np
+    from oracle import oracle as O
+    o = O.Oracle.from_trs(w.trs)
+    order = np.random.default_rng(7174).permutation(len(w.terms))
+    apps, secs, used = 0, 0.0, 0
+    t_wall = time.time()
+    for i in order:
+        r = o.run(w.terms[int(i)], with_nf=False)
+        apps += r.steps
+        secs += r.seconds
+        used += 1
+        if secs >= budget_s or time.time() - t_wall > 3 * budget_s:
+            break
+    o.close()
+    return {"value": apps / secs if secs > 0 else None, "unit": "rule applications/s",
+            "cores": 1, "kind": "oracle",
+            "sample": f"{used} of {len(w.terms)} terms of {w.name} in a seeded order, "
+                      f"{apps} rule applications, {secs:.2f} s of normalisation on one core"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="cfg3")
+    ap.add_argument("--mode", default="plain", choices=["plain", "frontier"])
+    ap.add_argument("--persistent", action="store_true")
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--npt", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); the batched "
+              "workload would shard by giving each GPU its own pool and share of the terms, "
+              "which is not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2009_07174_amd import trs as T
+
+    log(f"[bench] building workload {args.workload}")
+    w = make_workload(args.workload)
+    log(f"[bench] {w.name}: {w.n_terms} terms, {w.initial_nodes} initial nodes, "
+        f"pool {w.pool_slots} slots")
+    ctx = T.Context(w.pool_slots, w.maxarity)
+    ctx.load_trs(w.trs)
+    off, code = w.packed()
+    ctx.load_terms(off, code)
+    mode = {"plain": T.TRS_MODE_PLAIN, "frontier": T.TRS_MODE_FRONTIER}[args.mode]
+    opts = T.Options(block=args.block, nodes_per_thread=args.npt, mode=mode,
+                     persistent=1 if args.persistent else 0)
+    stream = torch.cuda.current_stream()
+    for i in range(args.warmup):
+        st = ctx.normalize(opts)
+        log(f"[bench] warmup {i}: {st['rounds']} rounds, {st['rule_apps']} rule apps, "
+            f"{st['device_ms']:.1f} ms")
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    stats = []
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for i in range(args.steps):
+        st = ctx.normalize(opts)
+        stats.append(st)
+        log(f"[bench] step {i}: {st['rounds']} rounds, {st['rule_apps']} rule apps, "
+            f"{st['device_ms']:.1f} ms")
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = ev0.elapsed_time(ev1)
+    ms_per_step = 1e3 * wall / args.steps
+    st = stats[-1]
+    apps = st["rule_apps"]
+    value = apps * args.steps / wall
+    dev_ms = sum(s["device_ms"] for s in stats) / len(stats)
+    A = w.maxarity
+    ab = algorithmic_bytes(st, A)
+    # round kernel: average over the rounds of the step, from the HIP events
+    # bracketing the timed region on the library's stream
+    rounds = st["rounds"]
+    ev_ms_step = ev_ms / args.steps
+    achieved = ab["total"] / (ev_ms_step * 1e-3) / 1e9
+    res = {
+        "metric": "rule applications/s + node-visits/s (HBM GB/s), plain vs learned frontier",
+        "value": value,
+        "unit": "rule applications/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "terms": w.n_terms, "initial_nodes": w.initial_nodes,
+                   "pool_slots": w.pool_slots, "maxarity": A, "mode": args.mode,
+                   "persistent": bool(args.persistent)},
+        "rule_apps": apps,
+        "node_visits_per_s": st["node_visits"] * args.steps / wall,
+        "rounds": rounds,
+        "device_ms_per_step": dev_ms,
+        "event_ms_per_step": ev_ms_step,
+        "us_per_round": 1e3 * ev_ms_step / max(rounds, 1),
+        "peak_slots": st["peak_slots"],
+        "rc_atomics_per_s": st["rc_atomics"] * args.steps / wall,
+        "algorithmic_bytes": ab,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+                     "kernel": "k_round", "launches_per_step": st["launches"],
+                     "bytes_per_launch": ab["total"] / max(st["launches"], 1),
+                     "avg_launch_us": 1e3 * ev_ms_step / max(st["launches"], 1)},
+        "stats": st,
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] CPU baseline (oracle, one core)")
+        res["cpu_baseline"] = cpu_baseline(w)
+    ctx.close()
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

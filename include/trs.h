@@ -115,6 +115,11 @@ typedef struct {
   int64_t mlp_evals;     /* learned mode: predictor evaluations */
   int64_t full_sweeps;   /* frontier modes: full confirmation sweeps */
   int64_t launches;      /* kernel launches issued for the round loop */
+  int64_t ready_visits;  /* active slots whose arguments were all normal forms */
+  int64_t nf_set;        /* slots that became normal forms without a rule */
+  int64_t rc_atomics;    /* reference-count atomic operations */
+  int64_t memo_blocked;  /* active slots found still blocked by the argument
+                            recorded at their previous examination */
   double device_ms;      /* device time of the round loop (HIP events) */
 } trs_stats;
 
@@ -158,6 +163,28 @@ int64_t trs_device_bytes(int64_t pool_slots, int32_t maxarity);
 
 /* Default options (mode plain, tuned block and nodes per thread). */
 void trs_default_opts(trs_opts *opts);
+
+/* Memory microbenchmarks of a device: the paper's comparison of aligned and
+ * random-access bandwidth (Section 4, hardware table), re-measured on this
+ * GPU, plus the latencies that bound one rewrite round.  Allocates and frees
+ * about 2 GiB of device memory; takes a few seconds. */
+typedef struct {
+  double stream_read_gbps;      /* coalesced 16-byte reads of 2 GiB */
+  double gather4_hbm_gops;      /* random 4-byte reads over 2 GiB, 1e9/s */
+  double gather4_llc_gops;      /* random 4-byte reads over 64 MiB, 1e9/s */
+  double gather1_llc_gops;      /* random 1-byte reads over 64 MiB, 1e9/s */
+  double atomic_random_gops;    /* random non-returning atomic adds, 1e9/s */
+  double load_latency_far_ns;   /* dependent load, 512 MiB random cycle */
+  double load_latency_near_ns;  /* dependent load, 256 KiB random cycle */
+  double atomic_latency_ns;     /* dependent returning atomic */
+  double empty_kernel_us;       /* back-to-back launch of an empty kernel */
+  double clock_mhz;
+  int64_t l2_bytes;
+  int32_t cu_count;
+  int32_t pad;
+} trs_membench_result;
+
+trs_status trs_membench(int32_t device, trs_membench_result *out);
 
 const char *trs_status_str(trs_status s);
 const char *trs_last_error(trs_ctx *ctx);

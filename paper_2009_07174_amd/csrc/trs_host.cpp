@@ -41,8 +41,9 @@ struct trs_ctx {
   int n_terms = 0;
   std::vector<int32_t> roots;
   int64_t n_init = 0;
-  std::vector<int32_t> img_hss, img_args, img_rc;
+  std::vector<int32_t> img_hss, img_args, img_rc, img_par;
   std::vector<uint8_t> img_state;
+  bool img_on_device = false;  // pristine copy uploaded since the last load_terms
 
   // device side
   bool dev_ready = false;
@@ -51,6 +52,12 @@ struct trs_ctx {
   Pool pool{};
   Ctl *d_ctl = nullptr;
   Ctl *h_ctl = nullptr;  // pinned
+  // pristine device copy of the initial pool image (restored D2D by every
+  // normalisation, so repeated runs need no host transfer)
+  int32_t *d_img_hss = nullptr, *d_img_args = nullptr, *d_img_rc = nullptr;
+  int32_t *d_img_par = nullptr;
+  uint8_t *d_img_state = nullptr;
+  int32_t stamp_base = 1;  // notification stamps of the next run start here
   int32_t *d_tab = nullptr;
   unsigned long long *d_bar = nullptr;
   std::vector<void *> owned;
@@ -60,7 +67,7 @@ struct trs_ctx {
   // captured chunk of rounds (one launch per round)
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
-  int g_grid = 0, g_block = 0, g_npt = 0, g_k = 0;
+  int g_grid = 0, g_block = 0, g_npt = 0, g_k = 0, g_mode = -1, g_cont = 0;
   size_t g_lds = 0;
 
   // results of the last normalisation
@@ -260,6 +267,26 @@ trs_status compile_rule(int rid, const std::vector<int32_t> &arity,
     *msg = "rule " + std::to_string(rid) + ": right-hand side creates too many nodes";
     return TRS_E_LIMIT;
   }
+  // parent hint of each new node: the first node that references it (the
+  // root, coded 0, or new node j, coded j+1)
+  std::vector<int> referrer(nn.size(), -1);
+  for (int o : rops)
+    if (o < 0 && referrer[-1 - o] < 0) referrer[-1 - o] = 0;
+  for (size_t j = 0; j < nn.size(); j++)
+    for (int o : nn[j].ops)
+      if (o < 0 && referrer[-1 - o] < 0) referrer[-1 - o] = (int)j + 1;
+  // a node is ready at birth when all its arguments are normal forms at birth
+  auto ready_ops = [&](const std::vector<int> &ops) {
+    for (int o : ops)
+      if (!(o >= 1 || nn[-1 - o].nf)) return false;
+    return true;
+  };
+  const bool root_ready = !var_root && !root_nf && ready_ops(rops);
+  for (auto &x : nn)
+    if (x.rc > 63) {
+      *msg = "rule " + std::to_string(rid) + ": a right-hand-side node is shared too often";
+      return TRS_E_LIMIT;
+    }
   std::vector<std::pair<int, int>> pos, neg;
   for (int k = 1; k <= npat; k++) {
     int d = refs[k] - (P[k].parent == 0 ? 1 : 0);
@@ -269,7 +296,8 @@ trs_status compile_rule(int rid, const std::vector<int32_t> &arity,
   std::vector<int32_t> &w = prog.words;
   w.assign(6, 0);
   w[0] = npat | ((int)nn.size() << 4) | ((int)var_root << 8) | ((int)root_nf << 9) |
-         ((int)pos.size() << 12) | ((int)neg.size() << 16) | (rootpat << 20);
+         ((int)root_ready << 10) | ((int)pos.size() << 12) | ((int)neg.size() << 16) |
+         (rootpat << 20);
   w[1] = rsym;
   w[5] = rid;
   for (int k = 1; k <= npat; k++) {
@@ -279,8 +307,11 @@ trs_status compile_rule(int rid, const std::vector<int32_t> &arity,
   w[2] = (int32_t)w.size();
   for (int o : rops) w.push_back(o);
   w[3] = (int32_t)w.size();
-  for (auto &x : nn) {
-    w.push_back(x.sym | (x.rc << 16) | ((int)x.nf << 24));
+  for (size_t j = 0; j < nn.size(); j++) {
+    const auto &x = nn[j];
+    const int rdy = !x.nf && ready_ops(x.ops);
+    w.push_back(x.sym | (x.rc << 16) | ((int)x.nf << 22) | (rdy << 23) |
+                (std::max(referrer[j], 0) << 24));
     for (int o : x.ops) w.push_back(o);
   }
   w[4] = (int32_t)w.size();
@@ -316,6 +347,17 @@ std::vector<Piece> device_pieces(trs_ctx *c, int64_t N, int A) {
       {(void **)&c->d_ctl, sizeof(Ctl)},
       {(void **)&c->d_tab, (size_t)TAB_MAX_WORDS * 4},
       {(void **)&c->d_bar, 256},
+      {(void **)&c->d_img_hss, (size_t)N * 4},
+      {(void **)&c->d_img_args, (size_t)N * A * 4},
+      {(void **)&c->d_img_rc, (size_t)N * 4},
+      {(void **)&c->d_img_state, (size_t)N},
+      {(void **)&c->d_img_par, (size_t)N * 4},
+      {(void **)&c->pool.par, (size_t)N * 4},
+      {(void **)&c->pool.front0, (size_t)N * 4},
+      {(void **)&c->pool.front1, (size_t)N * 4},
+      {(void **)&c->pool.ret0, (size_t)N * 4},
+      {(void **)&c->pool.ret1, (size_t)N * 4},
+      {(void **)&c->pool.qstamp, (size_t)N * 4},
   };
 }
 
@@ -360,6 +402,8 @@ trs_status device_init(trs_ctx *c) {
     }
   }
   c->pool.N = N;
+  HIPCHK(c, hipMemsetAsync(c->pool.qstamp, 0, (size_t)N * 4, c->stream));
+  c->stamp_base = 1;
   HIPCHK(c, hipHostMalloc((void **)&c->h_ctl, sizeof(Ctl), hipHostMallocDefault));
   HIPCHK(c, hipHostMalloc((void **)&c->h_zero, 64, hipHostMallocDefault));
   std::memset(c->h_zero, 0, 64);
@@ -379,7 +423,7 @@ int default_npt() { return 16; }
 extern "C" {
 
 int64_t trs_device_bytes(int64_t pool_slots, int32_t maxarity) {
-  if (pool_slots < 2 || pool_slots > INT32_MAX || maxarity < 1 || maxarity > 5) return -1;
+  if (pool_slots < 2 || pool_slots > (1ll << 29) || maxarity < 1 || maxarity > 5) return -1;
   trs_ctx tmp;
   return (int64_t)carve_bytes(device_pieces(&tmp, pool_slots, maxarity));
 }
@@ -408,7 +452,7 @@ void trs_default_opts(trs_opts *o) {
 trs_status trs_create(trs_ctx **out, const trs_config *cfg) {
   if (!out || !cfg) return TRS_E_ARG;
   *out = nullptr;
-  if (cfg->pool_slots < 2 || cfg->pool_slots > INT32_MAX) return TRS_E_ARG;
+  if (cfg->pool_slots < 2 || cfg->pool_slots > (1ll << 29)) return TRS_E_ARG;
   if (cfg->maxarity < 0 || cfg->maxarity > 5) return TRS_E_ARG;
   if (cfg->dev_mem && cfg->dev_bytes <= 0) return TRS_E_ARG;
   trs_ctx *c = new (std::nothrow) trs_ctx();
@@ -559,6 +603,7 @@ trs_status trs_load_terms(trs_ctx *c, int32_t n_terms, const int64_t *term_off,
   c->img_args.assign((size_t)(M + 1) * A, 0);
   c->img_rc.assign(M + 1, 0);
   c->img_state.assign(M + 1, ST_FREE);
+  c->img_par.assign(M + 1, 0);
   c->roots.assign(n_terms, 0);
   int64_t slot = 1;
   std::vector<std::pair<int64_t, int>> st;  // (parent slot, next arg)
@@ -574,6 +619,7 @@ trs_status trs_load_terms(trs_ctx *c, int32_t n_terms, const int64_t *term_off,
       c->img_rc[me] = 1;  // one parent, or the root-table entry
       if (!st.empty()) {
         c->img_args[(size_t)st.back().first * A + st.back().second] = (int32_t)me;
+        c->img_par[me] = (int32_t)st.back().first;
         st.back().second++;
       }
       if (c->arity[s] > 0) st.push_back({me, 0});
@@ -591,6 +637,7 @@ trs_status trs_load_terms(trs_ctx *c, int32_t n_terms, const int64_t *term_off,
   }
   c->n_terms = n_terms;
   c->terms_loaded = true;
+  c->img_on_device = false;
   return TRS_OK;
 }
 
@@ -602,7 +649,8 @@ trs_status trs_normalize(trs_ctx *c, const trs_opts *opts_in, trs_stats *stats) 
     o = *opts_in;
   else
     trs_default_opts(&o);
-  if (o.mode != TRS_MODE_PLAIN) return c->fail(TRS_E_ARG, "mode not available");
+  if (o.mode != TRS_MODE_PLAIN && o.mode != TRS_MODE_FRONTIER)
+    return c->fail(TRS_E_ARG, "mode not available");
   const int B = o.block ? o.block : default_block();
   const int npt = o.nodes_per_thread ? o.nodes_per_thread : default_npt();
   if (B < 64 || B > 1024 || (B & 63)) return c->fail(TRS_E_ARG, "block must be 64..1024, /64");
@@ -617,14 +665,37 @@ trs_status trs_normalize(trs_ctx *c, const trs_opts *opts_in, trs_stats *stats) 
   const int A = c->A;
   const int64_t M1 = c->n_init;
   hipStream_t s = c->stream;
-  HIPCHK(c, hipMemcpyAsync(c->pool.hss, c->img_hss.data(), M1 * 4, hipMemcpyHostToDevice, s));
-  HIPCHK(c, hipMemcpyAsync(c->pool.args, c->img_args.data(), M1 * A * 4, hipMemcpyHostToDevice, s));
-  HIPCHK(c, hipMemcpyAsync(c->pool.rc, c->img_rc.data(), M1 * 4, hipMemcpyHostToDevice, s));
-  HIPCHK(c, hipMemcpyAsync(c->pool.state, c->img_state.data(), M1, hipMemcpyHostToDevice, s));
+  if (!c->img_on_device) {
+    HIPCHK(c, hipMemcpyAsync(c->d_img_hss, c->img_hss.data(), M1 * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(c->d_img_args, c->img_args.data(), M1 * A * 4,
+                             hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(c->d_img_rc, c->img_rc.data(), M1 * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(c->d_img_state, c->img_state.data(), M1, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(c->d_img_par, c->img_par.data(), M1 * 4, hipMemcpyHostToDevice, s));
+    c->img_on_device = true;
+  }
+  HIPCHK(c, hipMemcpyAsync(c->pool.hss, c->d_img_hss, M1 * 4, hipMemcpyDeviceToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(c->pool.args, c->d_img_args, M1 * A * 4, hipMemcpyDeviceToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(c->pool.rc, c->d_img_rc, M1 * 4, hipMemcpyDeviceToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(c->pool.state, c->d_img_state, M1, hipMemcpyDeviceToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(c->pool.par, c->d_img_par, M1 * 4, hipMemcpyDeviceToDevice, s));
   HIPCHK(c, hipMemcpyAsync(c->d_tab, c->tab.data(), c->tab.size() * 4, hipMemcpyHostToDevice, s));
   std::memset(c->h_ctl, 0, sizeof(Ctl));
   c->h_ctl->n[0] = (int32_t)M1;
   c->h_ctl->peak_n = (int32_t)M1;
+  // notification stamps grow by the rounds of every run; restart them (and
+  // clear the stamp array) well before they could wrap
+  if (c->stamp_base > (1 << 30)) {
+    HIPCHK(c, hipMemsetAsync(c->pool.qstamp, 0, (size_t)c->cfg.pool_slots * 4, s));
+    c->stamp_base = 1;
+  }
+  c->h_ctl->stamp_base = c->stamp_base;
+  {
+    // round 0 is a full sweep; the launch that runs it needs one workgroup
+    // per tile (one in all when a single tile covers the pool)
+    const int64_t tiles = (M1 + (int64_t)B * npt - 1) / ((int64_t)B * npt);
+    c->h_ctl->next_need = (int32_t)std::max<int64_t>(1, tiles);
+  }
   HIPCHK(c, hipMemcpyAsync(c->d_ctl, c->h_ctl, sizeof(Ctl), hipMemcpyHostToDevice, s));
   unsigned long long zero = 0;
   HIPCHK(c, hipMemcpyAsync(c->d_bar, &zero, sizeof(zero), hipMemcpyHostToDevice, s));
@@ -639,6 +710,7 @@ trs_status trs_normalize(trs_ctx *c, const trs_opts *opts_in, trs_stats *stats) 
   ra.n_rules = c->n_rules;
   ra.npt = npt;
   ra.bar = c->d_bar;
+  ra.mode = o.mode;
   const size_t lds = trs_round_lds_bytes(B, npt, ra.tab_words, c->n_rules);
   if (lds > 160 * 1024) return c->fail(TRS_E_ARG, "configuration needs too much LDS");
   const int TILE = B * npt;
@@ -657,36 +729,46 @@ trs_status trs_normalize(trs_ctx *c, const trs_opts *opts_in, trs_stats *stats) 
     return (int)std::max<int64_t>(1, std::min<int64_t>(g, gmax));
   };
   int64_t r = 0, n_est = M1, launches = 0;
-  const int K = o.persistent ? 0 : 64;   // rounds per captured chunk
-  int P = 1;                             // chunks (or persistent launches) per poll
-  int KP = o.rounds_per_poll ? o.rounds_per_poll : 64;  // persistent rounds per launch
+  const int K = 64;        // launches per captured chunk (each runs >= 1 round)
+  int P = 1;               // chunks (or persistent launches) per poll
+  const int KP = o.rounds_per_poll ? o.rounds_per_poll : 64;  // persistent rounds per launch
+  // one workgroup runs rounds alone while their lists hold at most this
+  // many items (a few passes of the workgroup), continuing for up to
+  // cont_rounds rounds inside one launch
+  ra.small_cap = 4 * B;
+  ra.cont_rounds = o.max_rounds > 0 ? (int)std::min<int64_t>(o.max_rounds + 1, 4096) : 4096;
   HIPCHK(c, hipEventRecord(c->ev0, s));
-  const size_t small = offsetof(Ctl, cnt);
+  const size_t small = offsetof(Ctl, stat);  // control words and round counters
+  int64_t front_est = 0;
   trs_status result = TRS_OK;
   for (;;) {
-    const int g = grid_for(n_est);
+    int g = grid_for(n_est);
+    if (o.mode != TRS_MODE_PLAIN && front_est > 0) {
+      // frontier rounds need only as many workgroups as queued items (twice
+      // the last observed count, as a power of two); the rare full sweeps
+      // stride over all tiles with the same grid.  A persistent grid also
+      // pays its device-wide barrier per workgroup.
+      int64_t need = std::max<int64_t>(8, (2 * front_est + B - 1) / B);
+      int64_t gg = 1;
+      while (gg < need) gg <<= 1;
+      g = (int)std::min<int64_t>(gg, g);
+    }
     if (o.persistent) {
       for (int i = 0; i < P; i++) {
-        int64_t k_here = KP;
-        if (o.max_rounds > 0) k_here = std::min<int64_t>(k_here, o.max_rounds + 1 - r);
-        if (k_here <= 0) break;
         HIPCHK(c, hipMemcpyAsync(c->d_bar, c->h_zero, 8, hipMemcpyHostToDevice, s));
-        ra.r0 = (int32_t)r;
-        ra.nrounds = (int32_t)k_here;
+        ra.nrounds = KP;
         HIPCHK(c, trs_launch_persistent(A, ra, g, B, s));
         launches++;
-        r += k_here;
       }
     } else {
       if (!c->gexec || c->g_grid != g || c->g_block != B || c->g_npt != npt || c->g_k != K ||
-          c->g_lds != lds) {
+          c->g_lds != lds || c->g_mode != o.mode || c->g_cont != ra.cont_rounds) {
         if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
         if (c->graph) (void)hipGraphDestroy(c->graph);
         c->gexec = nullptr;
         c->graph = nullptr;
         HIPCHK(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
         for (int k = 0; k < K; k++) {
-          ra.r0 = k;
           hipError_t e = trs_launch_round(A, ra, g, B, s);
           if (e != hipSuccess) {
             hipGraph_t junk;
@@ -694,7 +776,6 @@ trs_status trs_normalize(trs_ctx *c, const trs_opts *opts_in, trs_stats *stats) 
             return c->fail(TRS_E_HIP, std::string("capture: ") + hipGetErrorString(e));
           }
         }
-        HIPCHK(c, trs_launch_advance(c->d_ctl, K, s));
         HIPCHK(c, hipStreamEndCapture(s, &c->graph));
         HIPCHK(c, hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
         c->g_grid = g;
@@ -702,16 +783,17 @@ trs_status trs_normalize(trs_ctx *c, const trs_opts *opts_in, trs_stats *stats) 
         c->g_npt = npt;
         c->g_k = K;
         c->g_lds = lds;
+        c->g_mode = o.mode;
+        c->g_cont = ra.cont_rounds;
       }
       for (int i = 0; i < P; i++) {
         HIPCHK(c, hipGraphLaunch(c->gexec, s));
         launches += K;
-        r += K;
-        if (o.max_rounds > 0 && r > o.max_rounds) break;
       }
     }
     HIPCHK(c, hipMemcpyAsync(c->h_ctl, c->d_ctl, small, hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));
+    r = c->h_ctl->r_cur;
     if (c->h_ctl->abort) {
       result = c->fail(TRS_E_INTERNAL, "device-wide barrier timed out");
       break;
@@ -723,6 +805,9 @@ trs_status trs_normalize(trs_ctx *c, const trs_opts *opts_in, trs_stats *stats) 
     }
     // the extent at the start of the last issued round
     n_est = std::max<int64_t>(n_est, c->h_ctl->peak_n);
+    front_est = 0;
+    for (int k = 0; k < 3; k++)
+      front_est = std::max<int64_t>(front_est, c->h_ctl->cnt[k].front + c->h_ctl->cnt[k].dead);
     P = std::min(P * 2, o.rounds_per_poll ? 1 : 64);
   }
   HIPCHK(c, hipEventRecord(c->ev1, s));
@@ -731,6 +816,7 @@ trs_status trs_normalize(trs_ctx *c, const trs_opts *opts_in, trs_stats *stats) 
   float ms = 0.f;
   HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
   const Ctl &h = *c->h_ctl;
+  c->stamp_base += (int32_t)std::min<int64_t>(r + 2, 1 << 30);
   if (result == TRS_OK && h.err) {
     result = c->fail(h.err, h.err == TRS_E_POOL ? "node pool exhausted during rewriting"
                                                 : "device reported an inconsistency");
@@ -756,8 +842,12 @@ trs_status trs_normalize(trs_ctx *c, const trs_opts *opts_in, trs_stats *stats) 
     stats->peak_slots = h.peak_n;
     stats->gc_rounds = h.gc_rounds;
     stats->mlp_evals = sum(STAT_MLP);
-    stats->full_sweeps = 0;
+    stats->full_sweeps = h.full_sweeps;
     stats->launches = launches;
+    stats->ready_visits = sum(STAT_READY);
+    stats->nf_set = sum(STAT_NFSET);
+    stats->rc_atomics = sum(STAT_RCOPS);
+    stats->memo_blocked = sum(STAT_MEMO);
     stats->device_ms = ms;
   }
   if (result != TRS_OK) return result;

@@ -13,8 +13,10 @@ struct RoundArgs {
   int32_t n_sym;
   int32_t n_rules;
   int32_t npt;          // slots per thread per tile
-  int32_t r0;           // round offset of this launch from ctl->r_base
-  int32_t nrounds;      // rounds this launch may run (persistent kernel)
+  int32_t nrounds;      // rounds a persistent launch may run
+  int32_t cont_rounds;  // rounds workgroup 0 may continue alone in one launch
+  int32_t small_cap;    // list items one workgroup takes on alone
+  int32_t mode;         // 0 full sweeps, 1 frontier (full sweep when it is empty)
   unsigned long long *bar;  // grid barrier counter (persistent kernel)
 };
 
@@ -25,13 +27,11 @@ size_t trs_round_lds_bytes(int block, int npt, int tab_words, int n_rules);
 // or capturing with a given LDS size.
 hipError_t trs_prepare_kernels(int A, size_t lds_bytes);
 
-// One round per launch: round ctl->r_base + r0 (nrounds ignored).
+// One launch: round ctl->r_cur on the grid, then, while rounds stay small,
+// further rounds on workgroup 0 alone; advances ctl->r_cur.
 hipError_t trs_launch_round(int A, const RoundArgs &a, int grid, int block, hipStream_t s);
 
-// ctl->r_base += k (the closing node of a captured chunk of rounds).
-hipError_t trs_launch_advance(Ctl *ctl, int k, hipStream_t s);
-
-// Persistent cooperative kernel: rounds ctl->r_base + r0 .. + nrounds-1,
+// Persistent cooperative kernel: rounds ctl->r_cur .. + nrounds-1,
 // separated by device-wide barriers.  *a.bar must be zero at launch.  grid
 // must not exceed trs_max_resident().
 hipError_t trs_launch_persistent(int A, const RoundArgs &a, int grid, int block, hipStream_t s);

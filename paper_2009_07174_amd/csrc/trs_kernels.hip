@@ -9,26 +9,36 @@
 //      pushed on the free stack that the next round allocates from.  This is
 //      the paper's garbage collection with free-index reuse, driven by a list
 //      instead of a sweep of all reference counts.
-//   2. Sweep: every slot below n is examined (the topology-driven sweep of
-//      Section 3).  A workgroup streams a tile of state bytes with vector
-//      loads, retires round markers, and compacts the live non-normal-form
-//      slots of the tile into an LDS work list.
-//   3. Rewrite: the workgroup processes the work list densely.  A slot whose
-//      arguments are all normal forms is matched against the rules of its
-//      head symbol in priority order (Section 2, rewrite_f) using the
-//      compiled per-symbol tables held in LDS; the first match is contracted
-//      in place (Section 3): the right-hand-side root overwrites the slot,
-//      new subterms go to slots taken from the free stack or past n, and
-//      reference counts are adjusted, increments before decrements.  A slot
-//      with no applicable rule becomes a normal form.
+//   2. Examination: in a full round every slot below n is examined (the
+//      topology-driven sweep of Section 3): a workgroup streams a tile of
+//      state bytes with vector loads, retires round markers, and compacts the
+//      live non-normal-form slots into an LDS work list.  In a frontier round
+//      only the slots queued by the previous round are examined.
+//   3. Rewrite: a slot whose arguments are all normal forms is matched
+//      against the rules of its head symbol in priority order (Section 2,
+//      rewrite_f) using the compiled per-symbol tables held in LDS; the first
+//      match is contracted in place (Section 3): the right-hand-side root
+//      overwrites the slot, new subterms go to slots taken from the free
+//      stack or past n, and reference counts are adjusted, increments before
+//      decrements.  A slot with no applicable rule becomes a normal form.
+//
+// Frontier modes add a data-driven queue to the topology-driven sweep (the
+// paper chose the sweep because thousands of threads contending on a queue
+// was the bottleneck on its GPU; here every append is aggregated per
+// workgroup).  A node is queued for the next round when it is created or
+// rewritten with all arguments already normal forms, or when one of its
+// arguments becomes a normal form (through the parent hint of that argument).
+// A round with an empty queue is a full sweep, and only a full sweep that
+// finds no live non-normal-form slot ends the run, so the method's own test
+// stays the judge of the result.
 //
 // Allocation takes one atomic per workgroup pass: a wave-level prefix sum of
 // the per-lane node counts, then a workgroup scan of the wave totals, then a
 // single fetch-add on the round's claim counter.  Claims below the free-stack
-// size map to recycled slots, the rest to fresh slots n, n+1, ...  (the
+// size map to recycled slots, the rest to fresh slots n, n+1, ... (the
 // paper's get_new_index with next_free_begin / next_fresh, without per-thread
-// atomics).  Dead-list appends are buffered in LDS and flushed with one
-// atomic per pass.
+// atomics).  Dead-list, frontier and retire-list appends are buffered in LDS
+// and flushed with one atomic per list per pass.
 //
 // Round-to-round state lives in the device control block, triple-buffered by
 // round (r % 3), so consecutive rounds need no host involvement and the
@@ -39,7 +49,7 @@
 
 #define MAXPAT 8
 #define MAXNEW 8
-#define DBUF_PER_THREAD 4
+#define QBUF_PER_THREAD 4
 
 namespace {
 
@@ -67,63 +77,99 @@ typedef int ivec4 __attribute__((ext_vector_type(4)));
 typedef int ivec8 __attribute__((ext_vector_type(8)));
 typedef int ivec16 __attribute__((ext_vector_type(16)));
 
+// An LDS-buffered append list: lanes append with an LDS atomic, the
+// workgroup flushes the buffer to the global list with one atomic.
+struct Queue {
+  int32_t *buf;     // LDS
+  int32_t *out;     // global list
+  int32_t *gcount;  // global length
+  int cap_lds;
+  int slot;         // index of the LDS counter in misc[]
+};
+
 struct Lds {
   int32_t *tab;
   int32_t *work;
-  int32_t *dbuf;
-  int32_t *misc;  // [0] work count [1] dbuf count [2] scratch base [3..18] wave sums
+  // misc: [0] work count [1..3] queue counts [4..6] flush / reservation bases
+  //       [8..23] wave sums [32..39] statistics [47..62] second wave sums
+  //       [63] barrier flag
+  int32_t *misc;
   int32_t *rcnt;  // per-rule application counts of this workgroup
-  int dbuf_cap;
+  Queue qd, qf, qr;  // dead, frontier, retire
 };
 
-// Workgroup-wide reservation of m items on a global counter.  Returns this
-// lane's first index.  Must be called by every thread of the workgroup.
-__device__ __forceinline__ int wg_reserve(const Lds &L, int m, int32_t *counter) {
+__device__ __forceinline__ void qpush(const Lds &L, const Queue &q, int32_t v, int64_t cap) {
+  int i = atomicAdd(&L.misc[q.slot], 1);
+  if (i < q.cap_lds) {
+    q.buf[i] = v;
+  } else {  // LDS buffer full: append directly
+    int g = atomicAdd(q.gcount, 1);
+    if (g < cap) q.out[g] = v;
+  }
+}
+
+__device__ __forceinline__ void qreserve(const Lds &L, const Queue &q, int k) {
+  const int nb = min(L.misc[q.slot], q.cap_lds);
+  L.misc[4 + k] = nb > 0 ? atomicAdd(q.gcount, nb) : 0;
+}
+
+// Flush one LDS queue's buffered entries (whole workgroup; k = flush slot).
+__device__ __forceinline__ void qcopy(const Lds &L, const Queue &q, int k, int64_t cap) {
+  const int nb = min(L.misc[q.slot], q.cap_lds);
+  const int gb = L.misc[4 + k];
+  for (int i = threadIdx.x; i < nb; i += blockDim.x)
+    if ((int64_t)gb + i < cap) q.out[gb + i] = q.buf[i];
+}
+
+// Flush the three LDS queues (whole workgroup).
+__device__ __forceinline__ void qflush(const Lds &L, int64_t cap) {
+  __syncthreads();
+  // (each queue is named statically: selecting one at run time would force
+  // the workgroup's LDS descriptors into scratch memory)
+  if (threadIdx.x == 0)
+    qreserve(L, L.qd, 0);
+  else if (threadIdx.x == 1)
+    qreserve(L, L.qf, 1);
+  else if (threadIdx.x == 2)
+    qreserve(L, L.qr, 2);
+  __syncthreads();
+  qcopy(L, L.qd, 0, cap);
+  qcopy(L, L.qf, 1, cap);
+  qcopy(L, L.qr, 2, cap);
+  __syncthreads();
+  if (threadIdx.x < 3) L.misc[1 + threadIdx.x] = 0;
+  __syncthreads();
+}
+
+// Workgroup-wide reservation of m1 items on counter c1 and m2 items on c2.
+// Returns this lane's first index for each.  Called by every thread.
+__device__ __forceinline__ int2 wg_reserve2(const Lds &L, int m1, int32_t *c1, int m2,
+                                            int32_t *c2) {
   const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  int incl = wave_incl_scan(m);
-  if (lane() == 63) L.misc[3 + w] = incl;
+  const int i1 = wave_incl_scan(m1), i2 = wave_incl_scan(m2);
+  if (lane() == 63) {
+    L.misc[8 + w] = i1;
+    L.misc[47 + w] = i2;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
-    int run = 0;
+    int r1 = 0, r2 = 0;
     for (int i = 0; i < nw; i++) {
-      int t = L.misc[3 + i];
-      L.misc[3 + i] = run;
-      run += t;
+      int t1 = L.misc[8 + i], t2 = L.misc[47 + i];
+      L.misc[8 + i] = r1;
+      L.misc[47 + i] = r2;
+      r1 += t1;
+      r2 += t2;
     }
-    L.misc[2] = run ? atomicAdd(counter, run) : 0;
+    L.misc[4] = r1 ? atomicAdd(c1, r1) : 0;
+    L.misc[5] = r2 ? atomicAdd(c2, r2) : 0;
   }
   __syncthreads();
-  int base = L.misc[2] + L.misc[3 + w] + incl - m;
-  __syncthreads();  // misc[2..] reused by the next call
-  return base;
-}
-
-__device__ __forceinline__ void dead_push(const Lds &L, int32_t slot, int32_t *gcount,
-                                          int32_t *dout, int64_t cap) {
-  int i = atomicAdd(&L.misc[1], 1);
-  if (i < L.dbuf_cap) {
-    L.dbuf[i] = slot;
-  } else {  // overflow of the LDS buffer: append directly
-    int g = atomicAdd(gcount, 1);
-    if (g < cap) dout[g] = slot;
-  }
-}
-
-// Flush the LDS dead buffer to the global dead list (whole workgroup).
-__device__ __forceinline__ void dead_flush(const Lds &L, int32_t *gcount, int32_t *dout,
-                                           int64_t cap) {
-  __syncthreads();
-  int nb = min(L.misc[1], L.dbuf_cap);
-  if (threadIdx.x == 0 && nb > 0) L.misc[2] = atomicAdd(gcount, nb);
-  __syncthreads();
-  if (nb > 0) {
-    int gb = L.misc[2];
-    for (int i = threadIdx.x; i < nb; i += blockDim.x)
-      if (gb + i < cap) dout[gb + i] = L.dbuf[i];
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) L.misc[1] = 0;
-  __syncthreads();
+  int2 b;
+  b.x = L.misc[4] + L.misc[8 + w] + i1 - m1;
+  b.y = L.misc[5] + L.misc[47 + w] + i2 - m2;
+  __syncthreads();  // misc reused by the next call
+  return b;
 }
 
 __device__ __forceinline__ int xcd_remap(int wg, int G) {
@@ -134,7 +180,7 @@ __device__ __forceinline__ int xcd_remap(int wg, int G) {
 }
 
 struct Counters {
-  int active, ready, fired, nfset, alloc, freed;
+  int active, ready, fired, nfset, alloc, freed, rcops, memo;
 };
 
 // visible normal form in round parity e (markers of the current parity are
@@ -143,46 +189,90 @@ __device__ __forceinline__ bool nf_visible(unsigned st, unsigned e) {
   return (st & ST_NF) && !((st & ST_PEND) && (((st >> 2) & 1u) == e));
 }
 
+// Rewrite a marker of round parity ep into the plain state.  Retire-list
+// entries are handled only in frontier rounds, where no other thread writes
+// the byte in the same round (a full round's sweep retires every marker
+// itself), so a plain byte store suffices.
+__device__ __forceinline__ void retire_marker(uint8_t *state, int s, unsigned ep) {
+  const unsigned b = state[s];
+  if (!(b & ST_PEND) || ((b >> 2) & 1u) != ep) return;
+  state[s] = (uint8_t)((b & ST_NF) ? ST_NF : ST_ACTIVE);
+}
+
+struct RoundCtx {
+  int r, n, fsP, mode;
+  unsigned e;
+  int stamp;
+  const int32_t *SP;
+  RoundCnt *cnt;
+};
+
+// Notify the parent of a node that just became a normal form (frontier modes).
+__device__ __forceinline__ void notify_parent(const RoundArgs &a, const Lds &L, const RoundCtx &R,
+                                              int s) {
+  const int par = a.p.par[s];
+  if (par > 0 && par < a.p.N) {
+    if (atomicExch(&a.p.qstamp[par], R.stamp) != R.stamp) qpush(L, L.qf, par, a.p.N);
+  }
+}
+
+// Examine slot s (s <= 0: idle lane) and rewrite it if it is a redex whose
+// arguments are all normal forms.  memo: the slot's memo bits.  Must be
+// called by every thread of the workgroup (contains the allocation barrier);
+// free_slot > 0: this lane also pushes that slot (a node collected in the
+// same pass) on the free stack SQ.
 template <int A>
-__device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, int s, int n,
-                                             int r, const int32_t *SP, int fsP, int32_t *dout,
-                                             RoundCnt *cnt, Counters &C) {
+__device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, const RoundCtx &R,
+                                             int s, int memo, bool memo_checked, int free_slot,
+                                             int32_t *SQ, int fsQ, Counters &C) {
   const Pool &p = a.p;
   const int32_t *tab = L.tab;
-  const unsigned e = (unsigned)(r & 1);
+  const unsigned e = R.e;
   const int64_t N = p.N;
+  const bool frontier = R.mode != 0;
+  RoundCnt *cnt = R.cnt;
   bool have = s > 0;
   int info = 0, ar = 0;
   ivec8 av = (ivec8)(0);
   bool ready = false;
   if (have) {
-    int f = p.hss[s];
-    if ((unsigned)f >= (unsigned)a.n_sym) {
-      cnt->err = -9;
-      have = false;
-    } else {
-      info = tab[TAB_SYM + f];
-      ar = info & 0xff;
-      ready = true;
+    if (!memo_checked) C.active++;
+    bool blocked = false;
+    if (memo && !memo_checked) {  // the argument that blocked the node last time
+      const int c = p.args[(int64_t)s * A + (memo - 1)];
+      if ((unsigned)c < (unsigned)N && c != 0) blocked = !nf_visible(p.state[c], e);
+      C.memo += blocked;
+    }
+    if (!blocked) {
+      const int f = p.hss[s];
+      if ((unsigned)f >= (unsigned)a.n_sym) {
+        cnt->err = -9;
+      } else {
+        info = tab[TAB_SYM + f];
+        ar = info & 0xff;
+        bool ok = true;
 #pragma unroll
-      for (int j = 0; j < A; j++) {
-        if (j < ar) {
-          int c = p.args[(int64_t)s * A + j];
-          if ((unsigned)c >= (unsigned)N || c == 0) {
-            cnt->err = -9;
-            ready = false;
+        for (int j = 0; j < A; j++) {
+          if (j < ar) {
+            const int c = p.args[(int64_t)s * A + j];
+            if ((unsigned)c >= (unsigned)N || c == 0) ok = false;
+            av[j] = c;
           }
-          av[j] = c;
         }
-      }
-      if (ready) {
+        if (!ok) {
+          cnt->err = -9;
+        } else {
+          int first_blocked = 0;
 #pragma unroll
-        for (int j = 0; j < A; j++)
-          if (j < ar) ready = ready && nf_visible(p.state[av[j]], e);
+          for (int j = A - 1; j >= 0; j--)
+            if (j < ar && !nf_visible(p.state[av[j]], e)) first_blocked = j + 1;
+          ready = first_blocked == 0;
+          if (!ready && first_blocked != memo)
+            p.state[s] = (uint8_t)(ST_ACTIVE | (first_blocked << ST_MEMO_SHIFT));
+        }
       }
     }
   }
-  C.active += have;
   int prog = -1;
   bool nfset = false;
   ivec16 ps = (ivec16)(0);  // ps[k]: slot matched by pattern node k (0 = the redex)
@@ -230,14 +320,21 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, i
   const int hdr = prog >= 0 ? tab[prog] : 0;
   const int m = (hdr >> 4) & 15;
   C.alloc += m;
-  const int claim = wg_reserve(L, m, &cnt->alloc);
+  const int2 base = wg_reserve2(L, m, &cnt->alloc, free_slot > 0 ? 1 : 0, &cnt->push);
+  if (free_slot > 0) {
+    if ((int64_t)fsQ + base.y < N)
+      SQ[fsQ + base.y] = free_slot;
+    else
+      cnt->err = -9;
+  }
   ivec8 ns = (ivec8)(0);  // slots of the new nodes
   bool okalloc = true;
 #pragma unroll
   for (int j = 0; j < MAXNEW; j++) {
     if (j < m) {
-      const int c = claim + j;
-      int64_t slot = (c < fsP) ? (int64_t)SP[fsP - 1 - c] : (int64_t)n + (c - fsP);
+      const int c = base.x + j;
+      const int64_t slot =
+          (c < R.fsP) ? (int64_t)R.SP[R.fsP - 1 - c] : (int64_t)R.n + (c - R.fsP);
       if (slot >= N || slot <= 0) okalloc = false;
       ns[j] = (int)slot;
     }
@@ -251,13 +348,14 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, i
     C.fired++;
     const int rsym = tab[prog + 1];
     const int ro = tab[prog + 2], no = tab[prog + 3], dl = tab[prog + 4], rid = tab[prog + 5];
-    const bool var_root = (hdr >> 8) & 1, root_nf = (hdr >> 9) & 1;
+    const bool var_root = (hdr >> 8) & 1, root_nf = (hdr >> 9) & 1, root_ready = (hdr >> 10) & 1;
     const int npos = (hdr >> 12) & 15, nneg = (hdr >> 16) & 15, rootpat = (hdr >> 20) & 15;
     // new nodes, children before parents
     int q = no;
     for (int j = 0; j < m; j++) {
       const int h = tab[q];
-      const int sym = h & 0xffff, rci = (h >> 16) & 0xff, bnf = (h >> 24) & 1;
+      const int sym = h & 0xffff, rci = (h >> 16) & 0x3f, bnf = (h >> 22) & 1;
+      const int nready = (h >> 23) & 1, refr = (h >> 24) & 15;
       const int ar2 = tab[TAB_SYM + sym] & 0xff;
       const int slot = ns[j];
 #pragma unroll
@@ -270,6 +368,15 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, i
       p.hss[slot] = sym;
       p.rc[slot] = rci;
       p.state[slot] = bnf ? (uint8_t)ST_NF : (uint8_t)(ST_ACTIVE | ST_PEND | (e << 2));
+      if (frontier) {
+        p.par[slot] = refr ? ns[refr - 1] : s;
+        if (!bnf) {
+          if (nready)
+            qpush(L, L.qf, slot, N);  // examined next round (retires its own marker)
+          else
+            qpush(L, L.qr, slot, N);
+        }
+      }
       q += 1 + ar2;
     }
     // the redex root is overwritten in place
@@ -286,14 +393,20 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, i
         if (j < sar) {
           const int cj = p.args[(int64_t)src * A + j];
           p.args[(int64_t)s * A + j] = cj;
-          if ((unsigned)cj < (unsigned)N)
+          if ((unsigned)cj < (unsigned)N) {
             atomicAdd(&p.rc[cj], 1);
-          else
+            C.rcops++;
+          } else {
             cnt->err = -9;
+          }
         }
       }
       p.hss[s] = sh;
       p.state[s] = pend_nf;
+      if (frontier) {
+        notify_parent(a, L, R, s);
+        qpush(L, L.qr, s, N);
+      }
     } else {
       const int rar = tab[TAB_SYM + rsym] & 0xff;
 #pragma unroll
@@ -304,7 +417,16 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, i
         }
       }
       p.hss[s] = rsym;
-      if (root_nf) p.state[s] = pend_nf;
+      if (root_nf) {
+        p.state[s] = pend_nf;
+        if (frontier) {
+          notify_parent(a, L, R, s);
+          qpush(L, L.qr, s, N);
+        }
+      } else {
+        if (memo) p.state[s] = (uint8_t)ST_ACTIVE;  // the arguments changed: drop the memo
+        if (frontier && root_ready) qpush(L, L.qf, s, N);
+      }
     }
     // reference counts: increments first, then decrements (a decrement that
     // reaches zero puts the node on the dead list)
@@ -317,24 +439,72 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, i
       const int d = (int)(int8_t)((dw >> 8) & 0xff);
       const int slot = ps[dw & 0xff];
       const int old = atomicAdd(&p.rc[slot], d);
-      if (old + d == 0) dead_push(L, slot, &cnt->dead, dout, N);
+      if (old + d == 0) qpush(L, L.qd, slot, N);
     }
+    C.rcops += npos + nneg;
     atomicAdd(&L.rcnt[rid], 1);
   } else if (nfset) {
     C.nfset++;
     p.state[s] = pend_nf;
+    if (frontier) {
+      notify_parent(a, L, R, s);
+      qpush(L, L.qr, s, N);
+    }
   }
+  qflush(L, N);
 }
 
-// The body of round r.  Returns false when the fixpoint was detected at the
-// start of the round (uniformly for all workgroups).
+// Collect dead node d: drop one reference to each argument, mark the slot
+// free.  Returns d if it is to be pushed on the free stack, else 0.
 template <int A>
-__device__ bool round_body(const RoundArgs &a, const Lds &L, int r) {
+__device__ __forceinline__ int collect(const RoundArgs &a, const Lds &L, RoundCnt *cnt, int d,
+                                       Counters &C) {
+  const Pool &p = a.p;
+  if ((unsigned)d >= (unsigned)p.N || d == 0) {
+    cnt->err = -9;
+    return 0;
+  }
+  const int f = p.hss[d];
+  const int ar = ((unsigned)f < (unsigned)a.n_sym) ? (L.tab[TAB_SYM + f] & 0xff) : 0;
+#pragma unroll
+  for (int j = 0; j < A; j++) {
+    if (j < ar) {
+      const int c = p.args[(int64_t)d * A + j];
+      if ((unsigned)c >= (unsigned)p.N || c == 0) {
+        cnt->err = -9;
+        continue;
+      }
+      const int old = atomicSub(&p.rc[c], 1);
+      C.rcops++;
+      if (old == 1) qpush(L, L.qd, c, p.N);
+    }
+  }
+  p.state[d] = (uint8_t)ST_FREE;
+  C.freed++;
+  return d;
+}
+
+// State of round r, derived from the counters of round r-1.
+struct RoundState {
+  int r, n, fs0, fs1, nd, nfront, nret, nlist, ntiles, need, err;
+  bool stop, quiescent, full;
+};
+
+// Thread 0 reads the previous round's counters and derives round r; the
+// values reach the workgroup through LDS.  Writes nothing.  need: number of
+// workgroups the round uses -- 1 when its lists are small (at most
+// small_cap items), so that one workgroup can run consecutive small rounds.
+// Derive round r from the counters of round r-1 (one thread; reads only).
+// need: number of workgroups the round uses -- 1 when its lists are small
+// (at most small_cap items), so that one workgroup can run consecutive small
+// rounds.
+__device__ RoundState round_state(const RoundArgs &a, int r) {
   const Pool &p = a.p;
   Ctl *ctl = a.ctl;
-  const int B = blockDim.x, tid = threadIdx.x, wg = blockIdx.x, G = gridDim.x;
-  const int r3 = r % 3;
-  int n, fs0, fs1, nd = 0;
+  const int B = blockDim.x;
+  RoundState rs;
+  int n, fs0, fs1, nd = 0, nfront = 0, nret = 0, err = 0;
+  bool quiescent = false, stop = false;
   if (r == 0) {
     n = ld(&ctl->n[0]);
     fs0 = ld(&ctl->fs[0][0]);
@@ -343,7 +513,9 @@ __device__ bool round_body(const RoundArgs &a, const Lds &L, int r) {
     const int p3 = (r + 2) % 3;
     const int c_alloc = ld(&ctl->cnt[p3].alloc), c_push = ld(&ctl->cnt[p3].push);
     const int c_dead = ld(&ctl->cnt[p3].dead), c_act = ld(&ctl->cnt[p3].active);
-    const int c_err = ld(&ctl->cnt[p3].err);
+    const int c_err = ld(&ctl->cnt[p3].err), c_full = ld(&ctl->cnt[p3].full);
+    nfront = ld(&ctl->cnt[p3].front);
+    nret = ld(&ctl->cnt[p3].ret);
     const int pn = ld(&ctl->n[p3]), pf0 = ld(&ctl->fs[p3][0]), pf1 = ld(&ctl->fs[p3][1]);
     const int P = (r - 1) & 1;  // stack popped in round r-1
     const int fsP = P ? pf1 : pf0;
@@ -358,142 +530,265 @@ __device__ bool round_body(const RoundArgs &a, const Lds &L, int r) {
       fs0 = pf0 + c_push;
     }
     nd = c_dead;
-    const bool stop = c_err != 0 || (c_act == 0 && c_dead == 0) || nn > p.N;
-    if (stop) {
-      if (wg == 0 && tid == 0) {
-        ctl->done = 1;
-        ctl->done_round = r;
-        ctl->err = c_err ? c_err : (nn > p.N ? -5 : 0);
-        ctl->n_final = n;
-      }
-      return false;
-    }
+    // a full round that met no live non-normal-form slot: nothing can be
+    // rewritten any more; remaining rounds only collect
+    quiescent = c_full && c_act == 0;
+    stop = c_err != 0 || nn > p.N || (quiescent && c_dead == 0);
+    err = c_err ? c_err : (nn > p.N ? -5 : 0);
   }
+  if (quiescent) nfront = 0;
+  rs.r = r;
+  rs.n = n;
+  rs.fs0 = fs0;
+  rs.fs1 = fs1;
+  rs.nd = nd;
+  rs.nfront = nfront;
+  rs.nret = nret;
+  rs.stop = stop;
+  rs.quiescent = quiescent;
+  rs.err = err;
+  rs.full = !quiescent && (a.mode == 0 || nfront == 0 || r == 0);
+  // in full rounds the sweep retires every marker, so the retire list is
+  // skipped
+  rs.nlist = nd + (rs.full ? 0 : nret + nfront);
+  rs.ntiles = rs.full ? (n + B * a.npt - 1) / (B * a.npt) : 0;
+  rs.need = max((rs.nlist + B - 1) / B, rs.ntiles);
+  if (rs.ntiles <= 1 && rs.nlist <= a.small_cap) rs.need = 1;
+  if (stop) rs.need = 1;
+  return rs;
+}
+
+// round_state computed by thread 0 and shared with the workgroup via LDS.
+__device__ RoundState round_prepare(const RoundArgs &a, const Lds &L, int r) {
+  int32_t *bc = L.misc + 40;  // [40..46]
+  if (threadIdx.x == 0) {
+    const RoundState t = round_state(a, r);
+    bc[0] = t.n;
+    bc[1] = t.fs0;
+    bc[2] = t.fs1;
+    bc[3] = t.nd;
+    bc[4] = t.nfront;
+    bc[5] = t.nret;
+    bc[6] = (t.stop ? 1 : 0) | (t.quiescent ? 2 : 0) | (t.err << 8);
+  }
+  __syncthreads();
+  RoundState rs;
+  const int B = blockDim.x;
+  rs.r = r;
+  rs.n = bc[0];
+  rs.fs0 = bc[1];
+  rs.fs1 = bc[2];
+  rs.nd = bc[3];
+  rs.nfront = bc[4];
+  rs.nret = bc[5];
+  rs.stop = bc[6] & 1;
+  rs.quiescent = bc[6] & 2;
+  rs.err = bc[6] >> 8;
+  __syncthreads();
+  rs.full = !rs.quiescent && (a.mode == 0 || rs.nfront == 0 || r == 0);
+  rs.nlist = rs.nd + (rs.full ? 0 : rs.nret + rs.nfront);
+  rs.ntiles = rs.full ? (rs.n + B * a.npt - 1) / (B * a.npt) : 0;
+  rs.need = max((rs.nlist + B - 1) / B, rs.ntiles);
+  if (rs.ntiles <= 1 && rs.nlist <= a.small_cap) rs.need = 1;
+  if (rs.stop) rs.need = 1;
+  return rs;
+}
+
+// Record the end of the run (thread 0 of workgroup 0).
+__device__ __forceinline__ void round_stop(const RoundArgs &a, const RoundState &rs) {
+  Ctl *ctl = a.ctl;
+  ctl->done = 1;
+  ctl->done_round = rs.r;
+  ctl->err = rs.err;
+  ctl->n_final = rs.n;
+}
+
+// Execute round rs.r: bookkeeping by workgroup 0, then this workgroup's
+// share of the lists and of the sweep.  Called only by workgroups below
+// rs.need; tables must be in LDS.
+template <int A>
+__device__ void round_execute(const RoundArgs &a, Lds &L, const RoundState &rs) {
+  const Pool &p = a.p;
+  Ctl *ctl = a.ctl;
+  const int B = blockDim.x, tid = threadIdx.x, wg = blockIdx.x;
+  const int r = rs.r, r3 = r % 3, mode = a.mode;
+  const int n = rs.n, fs0 = rs.fs0, fs1 = rs.fs1, nd = rs.nd, nret = rs.nret, nfront = rs.nfront;
+  const bool full = rs.full, quiescent = rs.quiescent;
+  const int nlist = rs.nlist, ntiles = rs.ntiles, need = rs.need;
+  const int G = gridDim.x;
   if (wg == 0 && tid == 0) {
     ctl->n[r3] = n;
     ctl->fs[r3][0] = fs0;
     ctl->fs[r3][1] = fs1;
     RoundCnt *nx = &ctl->cnt[(r + 1) % 3];
-    nx->alloc = nx->push = nx->dead = nx->active = nx->err = nx->front = 0;
+    nx->alloc = nx->push = nx->dead = nx->active = nx->err = nx->front = nx->ret = nx->full = 0;
+    ctl->cnt[r3].full = (full || quiescent) ? 1 : 0;
     if (n > ctl->peak_n) ctl->peak_n = n;
     if (nd > 0) ctl->gc_rounds++;
-    ctl->stat[STAT_VISITS][0] += (unsigned long long)n;
+    if (full) ctl->full_sweeps++;
+    ctl->stat[STAT_VISITS][0] += (unsigned long long)(full ? n : nfront);
   }
+  // the first `need` workgroups run the round; list items and tiles are
+  // strided over exactly those
+  const int Ga = min(G, need);
   RoundCnt *cnt = &ctl->cnt[r3];
-  Counters C = {0, 0, 0, 0, 0, 0};
-  int32_t *dout = (r & 1) ? p.dead1 : p.dead0;
+  Counters C = {0, 0, 0, 0, 0, 0, 0, 0};
+  RoundCtx R;
+  R.r = r;
+  R.n = n;
+  R.e = (unsigned)(r & 1);
+  R.mode = mode;
+  R.cnt = cnt;
+  R.stamp = ld(&ctl->stamp_base) + r;
+  R.SP = (r & 1) ? p.fstack1 : p.fstack0;
+  R.fsP = (r & 1) ? fs1 : fs0;
+  int32_t *SQ = ((r + 1) & 1) ? p.fstack1 : p.fstack0;
+  const int fsQ = ((r + 1) & 1) ? fs1 : fs0;
+  L.qd.out = (r & 1) ? p.dead1 : p.dead0;
+  L.qd.gcount = &cnt->dead;
+  L.qf.out = (r & 1) ? p.front1 : p.front0;
+  L.qf.gcount = &cnt->front;
+  L.qr.out = (r & 1) ? p.ret1 : p.ret0;
+  L.qr.gcount = &cnt->ret;
+  const int32_t *D = ((r - 1) & 1) ? p.dead1 : p.dead0;
+  const int32_t *F = ((r - 1) & 1) ? p.front1 : p.front0;
+  const int32_t *RT = ((r - 1) & 1) ? p.ret1 : p.ret0;
+  const unsigned ep = (unsigned)((r - 1) & 1);
 
-  // ---- 1. collection of the previous round's dead nodes
-  if (nd > 0) {
-    const int32_t *D = ((r - 1) & 1) ? p.dead1 : p.dead0;
-    int32_t *SQ = ((r + 1) & 1) ? p.fstack1 : p.fstack0;
-    const int fsQ = ((r + 1) & 1) ? fs1 : fs0;
-    for (int base = wg * B; base < nd; base += G * B) {
+  // ---- 1. list items: collection, marker retirement, frontier slots
+  {
+    const int nr_here = full ? 0 : nret;
+    for (int base = wg * B; base < nlist; base += Ga * B) {
       const int i = base + tid;
-      const bool v = i < nd;
-      int d = v ? D[i] : 0;
-      if (v && ((unsigned)d >= (unsigned)p.N || d == 0)) {
-        cnt->err = -9;
-        d = 0;
-      }
-      if (v && d) {
-        const int f = p.hss[d];
-        const int ar = ((unsigned)f < (unsigned)a.n_sym) ? (L.tab[TAB_SYM + f] & 0xff) : 0;
-#pragma unroll
-        for (int j = 0; j < A; j++) {
-          if (j < ar) {
-            const int c = p.args[(int64_t)d * A + j];
-            const int old = atomicSub(&p.rc[c], 1);
-            if (old == 1) dead_push(L, c, &cnt->dead, dout, p.N);
+      int s = 0, memo = 0, fslot = 0;
+      if (i < nd) {
+        fslot = collect<A>(a, L, cnt, D[i], C);
+      } else if (i < nd + nr_here) {
+        const int x = RT[i - nd];
+        if ((unsigned)x < (unsigned)p.N && x > 0) retire_marker(p.state, x, ep);
+      } else if (i < nlist) {
+        const int x = F[i - nd - nr_here];
+        if ((unsigned)x < (unsigned)p.N && x > 0) {
+          unsigned st = p.state[x];
+          if ((st & ST_PEND) && ((st >> 2) & 1u) != R.e) {  // retire its own marker
+            st = (st & ST_NF) ? ST_NF : ST_ACTIVE;
+            p.state[x] = (uint8_t)st;
+          }
+          if ((st & ST_ACTIVE) && !(st & ST_PEND)) {
+            s = x;
+            memo = (int)((st & ST_MEMO_MASK) >> ST_MEMO_SHIFT);
           }
         }
-        p.state[d] = (uint8_t)ST_FREE;
-        C.freed++;
       }
-      const int pos = wg_reserve(L, (v && d) ? 1 : 0, &cnt->push);
-      if (v && d) {
-        if ((int64_t)fsQ + pos < p.N)
-          SQ[fsQ + pos] = d;
-        else
-          cnt->err = -9;
-      }
-      dead_flush(L, &cnt->dead, dout, p.N);
+      process_slot<A>(a, L, R, s, memo, false, fslot, SQ, fsQ, C);
     }
   }
 
-  // ---- 2./3. sweep of all slots below n, rewrite of the ready ones
-  const int npt = a.npt;
-  const int TILE = B * npt;
-  const int ntiles = (n + TILE - 1) / TILE;
-  const unsigned e = (unsigned)(r & 1);
-  const int32_t *SP = (r & 1) ? p.fstack1 : p.fstack0;
-  const int fsP = (r & 1) ? fs1 : fs0;
-  for (int t = xcd_remap(wg, G); t < ntiles; t += G) {
-    const int base = t * TILE + tid * npt;
-    // state bytes of this thread's slots, kept in four registers
-    ivec4 sw = (ivec4)(0);
-    if (npt == 16) {
-      const uint4 v = *reinterpret_cast<const uint4 *>(p.state + base);
-      sw[0] = (int)v.x;
-      sw[1] = (int)v.y;
-      sw[2] = (int)v.z;
-      sw[3] = (int)v.w;
-    } else if (npt == 8) {
-      const uint2 v = *reinterpret_cast<const uint2 *>(p.state + base);
-      sw[0] = (int)v.x;
-      sw[1] = (int)v.y;
-    } else if (npt == 4) {
-      sw[0] = (int)*reinterpret_cast<const uint32_t *>(p.state + base);
-    } else {
-      for (int j = 0; j < npt; j++) sw[0] |= (int)p.state[base + j] << (8 * j);
-    }
-    for (int j = 0; j < npt; j++) {
-      const int slot = base + j;
-      const unsigned byte = ((unsigned)sw[j >> 2] >> ((j & 3) * 8)) & 0xffu;
-      unsigned st = (slot < n && slot > 0) ? byte : 0u;
-      if ((st & 0x7fu) == 0) continue;  // free or plain normal form
-      if (st & ST_PEND) {
-        if (((st >> 2) & 1u) == e) continue;  // created this round
-        const uint8_t nst = (st & ST_NF) ? (uint8_t)ST_NF : (uint8_t)ST_ACTIVE;
-        p.state[slot] = nst;
-        if (nst == ST_NF) continue;
+  // ---- 2./3. full sweep of all slots below n, rewrite of the ready ones
+  if (full) {
+    const int npt = a.npt;
+    const int TILE = B * npt;
+    const unsigned e = R.e;
+    for (int t = xcd_remap(wg, Ga); t < ntiles; t += Ga) {
+      const int base = t * TILE + tid * npt;
+      // state bytes of this thread's slots, kept in four registers
+      ivec4 sw = (ivec4)(0);
+      if (npt == 16) {
+        const uint4 v = *reinterpret_cast<const uint4 *>(p.state + base);
+        sw[0] = (int)v.x;
+        sw[1] = (int)v.y;
+        sw[2] = (int)v.z;
+        sw[3] = (int)v.w;
+      } else if (npt == 8) {
+        const uint2 v = *reinterpret_cast<const uint2 *>(p.state + base);
+        sw[0] = (int)v.x;
+        sw[1] = (int)v.y;
+      } else if (npt == 4) {
+        sw[0] = (int)*reinterpret_cast<const uint32_t *>(p.state + base);
+      } else {
+        for (int j = 0; j < npt; j++) sw[0] |= (int)p.state[base + j] << (8 * j);
       }
-      const int w = atomicAdd(&L.misc[0], 1);
-      L.work[w] = slot;
+      // classify the thread's slots; for live slots with a memo, read the
+      // recorded argument of all of them first, then all their states, so
+      // the dependent loads of the 16 slots overlap
+      ivec16 cidx = (ivec16)(0);   // memo argument slot (0: none)
+      int pending = 0;             // bit j: slot j is live and not in normal form
+#pragma unroll
+      for (int j = 0; j < 16; j++) {
+        if (j < npt) {
+          const int slot = base + j;
+          const unsigned byte = ((unsigned)sw[j >> 2] >> ((j & 3) * 8)) & 0xffu;
+          unsigned st = (slot < n && slot > 0) ? byte : 0u;
+          if ((st & 0x7fu) == 0) continue;  // free or plain normal form
+          if (st & ST_PEND) {
+            if (((st >> 2) & 1u) == e) continue;  // created this round
+            st = (st & ST_NF) ? ST_NF : ST_ACTIVE;
+            p.state[slot] = (uint8_t)st;
+            if (st == ST_NF) continue;
+          }
+          pending |= 1 << j;
+          const int memo = (int)((st & ST_MEMO_MASK) >> ST_MEMO_SHIFT);
+          if (memo) {
+            const int c = p.args[(int64_t)slot * A + (memo - 1)];
+            cidx[j] = ((unsigned)c < (unsigned)p.N) ? c : 0;
+          }
+        }
+      }
+      int cst[16];
+#pragma unroll
+      for (int j = 0; j < 16; j++) cst[j] = (pending >> j & 1) && cidx[j] ? p.state[cidx[j]] : 0;
+#pragma unroll
+      for (int j = 0; j < 16; j++) {
+        if (!(pending >> j & 1)) continue;
+        C.active++;
+        const int slot = base + j;
+        const unsigned byte = ((unsigned)sw[j >> 2] >> ((j & 3) * 8)) & 0xffu;
+        const int memo = (byte & ST_PEND) ? 0 : (int)((byte & ST_MEMO_MASK) >> ST_MEMO_SHIFT);
+        if (memo && cidx[j] && !nf_visible((unsigned)cst[j], e)) {
+          C.memo++;  // still blocked by the same argument
+          continue;
+        }
+        const int w = atomicAdd(&L.misc[0], 1);
+        L.work[w] = slot | (memo << 29);
+      }
+      __syncthreads();
+      const int W = L.misc[0];
+      for (int pb = 0; pb < W; pb += B) {
+        const int idx = pb + tid;
+        const int wv = idx < W ? L.work[idx] : 0;
+        process_slot<A>(a, L, R, wv & 0x1fffffff, (int)((unsigned)wv >> 29), true, 0, SQ, fsQ,
+                        C);
+      }
+      __syncthreads();
+      if (tid == 0) L.misc[0] = 0;
+      __syncthreads();
     }
-    __syncthreads();
-    const int W = L.misc[0];
-    for (int pb = 0; pb < W; pb += B) {
-      const int idx = pb + tid;
-      const int s = idx < W ? L.work[idx] : 0;
-      process_slot<A>(a, L, s, n, r, SP, fsP, dout, cnt, C);
-      dead_flush(L, &cnt->dead, dout, p.N);
-    }
-    __syncthreads();
-    if (tid == 0) L.misc[0] = 0;
-    __syncthreads();
   }
 
   // ---- per-workgroup statistics
-  atomicAdd(&L.misc[20], C.active);
-  atomicAdd(&L.misc[21], C.ready);
-  atomicAdd(&L.misc[22], C.fired);
-  atomicAdd(&L.misc[23], C.nfset);
-  atomicAdd(&L.misc[24], C.alloc);
-  atomicAdd(&L.misc[25], C.freed);
+  atomicAdd(&L.misc[32], C.active);
+  atomicAdd(&L.misc[33], C.ready);
+  atomicAdd(&L.misc[34], C.fired);
+  atomicAdd(&L.misc[35], C.nfset);
+  atomicAdd(&L.misc[36], C.alloc);
+  atomicAdd(&L.misc[37], C.freed);
+  atomicAdd(&L.misc[38], C.rcops);
+  atomicAdd(&L.misc[39], C.memo);
   __syncthreads();
   if (tid == 0) {
     const int sp = wg & (CTL_SPREAD - 1);
-    if (L.misc[20]) {
+    if (L.misc[32]) {
       cnt->active = 1;
-      atomicAdd(&ctl->stat[STAT_ACTIVE][sp], (unsigned long long)L.misc[20]);
+      atomicAdd(&ctl->stat[STAT_ACTIVE][sp], (unsigned long long)L.misc[32]);
     }
-    if (L.misc[21]) atomicAdd(&ctl->stat[STAT_READY][sp], (unsigned long long)L.misc[21]);
-    if (L.misc[22]) atomicAdd(&ctl->stat[STAT_FIRED][sp], (unsigned long long)L.misc[22]);
-    if (L.misc[23]) atomicAdd(&ctl->stat[STAT_NFSET][sp], (unsigned long long)L.misc[23]);
-    if (L.misc[24]) atomicAdd(&ctl->stat[STAT_ALLOC][sp], (unsigned long long)L.misc[24]);
-    if (L.misc[25]) atomicAdd(&ctl->stat[STAT_FREED][sp], (unsigned long long)L.misc[25]);
-    for (int i = 0; i < 20; i++) L.misc[20 + i] = 0;
+    if (L.misc[33]) atomicAdd(&ctl->stat[STAT_READY][sp], (unsigned long long)L.misc[33]);
+    if (L.misc[34]) atomicAdd(&ctl->stat[STAT_FIRED][sp], (unsigned long long)L.misc[34]);
+    if (L.misc[35]) atomicAdd(&ctl->stat[STAT_NFSET][sp], (unsigned long long)L.misc[35]);
+    if (L.misc[36]) atomicAdd(&ctl->stat[STAT_ALLOC][sp], (unsigned long long)L.misc[36]);
+    if (L.misc[37]) atomicAdd(&ctl->stat[STAT_FREED][sp], (unsigned long long)L.misc[37]);
+    if (L.misc[38]) atomicAdd(&ctl->stat[STAT_RCOPS][sp], (unsigned long long)L.misc[38]);
+    if (L.misc[39]) atomicAdd(&ctl->stat[STAT_MEMO][sp], (unsigned long long)L.misc[39]);
+    for (int i = 32; i < 40; i++) L.misc[i] = 0;
   }
   for (int i = tid; i < a.n_rules; i += B) {
     const int c = L.rcnt[i];
@@ -503,37 +798,103 @@ __device__ bool round_body(const RoundArgs &a, const Lds &L, int r) {
     }
   }
   __syncthreads();
-  return true;
 }
 
-__device__ __forceinline__ Lds setup_lds(const RoundArgs &a, int32_t *smem) {
+__device__ __forceinline__ Lds setup_lds(const RoundArgs &a, int32_t *smem, bool load_tab) {
   Lds L;
   const int B = blockDim.x;
   L.tab = smem;
   L.work = L.tab + ((a.tab_words + 3) & ~3);
-  L.dbuf = L.work + B * a.npt;
-  L.dbuf_cap = DBUF_PER_THREAD * B;
-  L.misc = L.dbuf + L.dbuf_cap;
+  int32_t *q = L.work + B * a.npt;
+  const int qc = QBUF_PER_THREAD * B;
+  L.qd.buf = q;
+  L.qf.buf = q + qc;
+  L.qr.buf = q + 2 * qc;
+  L.qd.cap_lds = L.qf.cap_lds = L.qr.cap_lds = qc;
+  L.qd.slot = 1;
+  L.qf.slot = 2;
+  L.qr.slot = 3;
+  L.misc = q + 3 * qc;
   L.rcnt = L.misc + 64;
-  for (int i = threadIdx.x; i < a.tab_words; i += B) L.tab[i] = a.tab[i];
+  if (load_tab)
+    for (int i = threadIdx.x; i < a.tab_words; i += B) L.tab[i] = a.tab[i];
   for (int i = threadIdx.x; i < 64; i += B) L.misc[i] = 0;
   for (int i = threadIdx.x; i < a.n_rules; i += B) L.rcnt[i] = 0;
   __syncthreads();
   return L;
 }
 
+__device__ __forceinline__ int bcast(const Lds &L, int v) {
+  if (threadIdx.x == 0) L.misc[31] = v;
+  __syncthreads();
+  const int x = L.misc[31];
+  __syncthreads();
+  return x;
+}
+
+__device__ __forceinline__ void load_tables(const RoundArgs &a, const Lds &L) {
+  for (int i = threadIdx.x; i < a.tab_words; i += blockDim.x) L.tab[i] = a.tab[i];
+  __syncthreads();
+}
+
+// One launch executes round ctl->r_cur on the whole grid.  When that round
+// is small enough for one workgroup, workgroup 0 runs it alone and then keeps
+// running the following rounds for as long as they stay small: every write
+// of those rounds is its own, so no device-wide synchronisation is needed
+// and their working set stays in its XCD's L2.  The last workgroup to finish
+// advances ctl->r_cur past the last round executed.
 template <int A>
 __global__ void __launch_bounds__(1024) k_round(RoundArgs a) {
   extern __shared__ int32_t smem[];
-  if (ld(&a.ctl->done)) return;
-  Lds L = setup_lds(a, smem);
-  round_body<A>(a, L, ld(&a.ctl->r_base) + a.r0);
-}
-
-// Advances the round base by the number of rounds a captured chunk holds
-// (the last node of the HIP graph of a chunk).
-__global__ void k_advance(Ctl *ctl, int k) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) ctl->r_base += k;
+  Ctl *ctl = a.ctl;
+  if (ld(&ctl->done)) return;
+  Lds L = setup_lds(a, smem, false);  // tables are loaded only by workgroups with work
+  const int wg = blockIdx.x, tid = threadIdx.x;
+  // the number of workgroups this launch's first round uses was published
+  // by the previous launch; the others leave without reading any round
+  // counter (workgroup 0 may already be running later rounds alone)
+  const int need0 = bcast(L, tid == 0 ? ld(&ctl->next_need) : 0);
+  int r = 0;
+  if (wg < need0) {
+    r = bcast(L, tid == 0 ? ld(&ctl->r_cur) : 0);
+    RoundState rs = round_prepare(a, L, r);
+    if (rs.stop) {
+      if (wg == 0 && tid == 0) round_stop(a, rs);
+      return;
+    }
+    if (rs.need != need0 && tid == 0) ctl->cnt[r % 3].err = -9;  // inconsistent counters
+    const bool alone = rs.need == 1;
+    load_tables(a, L);
+    // one call site: the first round, then (workgroup 0 alone) the
+    // following small rounds
+    for (int k = 0;; k++) {
+      round_execute<A>(a, L, rs);
+      if (!alone || k + 1 >= a.cont_rounds) break;
+      rs = round_prepare(a, L, rs.r + 1);
+      if (rs.stop) {
+        if (tid == 0) round_stop(a, rs);
+        return;
+      }
+      if (rs.need != 1) break;
+    }
+    if (alone && tid == 0)
+      __hip_atomic_store(&ctl->r_reached, rs.stop || rs.need == 1 ? rs.r + 1 : rs.r,
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    __threadfence();
+    const int t = atomicAdd(&ctl->ticket, 1);
+    if (t == (int)gridDim.x - 1) {
+      // last workgroup of the launch: every round it covered is complete
+      __threadfence();
+      const int rr = max(ld(&ctl->r_cur) + 1, ld(&ctl->r_reached));
+      const RoundState nx = round_state(a, rr);
+      __hip_atomic_store(&ctl->next_need, nx.need, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&ctl->ticket, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&ctl->r_cur, rr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
 }
 
 // Device-wide barrier for the persistent kernel.  The host zeroes *bar
@@ -571,14 +932,26 @@ __device__ __forceinline__ bool grid_barrier(unsigned long long *bar, unsigned l
 template <int A>
 __global__ void __launch_bounds__(1024) k_persistent(RoundArgs a) {
   extern __shared__ int32_t smem[];
-  if (ld(&a.ctl->done) || ld(&a.ctl->abort)) return;
-  Lds L = setup_lds(a, smem);
+  Ctl *ctl = a.ctl;
+  if (ld(&ctl->done) || ld(&ctl->abort)) return;
+  Lds L = setup_lds(a, smem, true);
   const unsigned long long G = gridDim.x;
-  const int r0 = ld(&a.ctl->r_base) + a.r0;
-  for (int k = 0; k < a.nrounds; k++) {
-    if (!round_body<A>(a, L, r0 + k)) return;
-    if (!grid_barrier(a.bar, G * (unsigned long long)(k + 1), &a.ctl->abort, &L.misc[63]))
+  const int r0 = bcast(L, threadIdx.x == 0 ? ld(&ctl->r_cur) : 0);
+  int r = r0;
+  for (int k = 0; k < a.nrounds; k++, r++) {
+    RoundState rs = round_prepare(a, L, r);
+    if (rs.stop) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) round_stop(a, rs);
       return;
+    }
+    if ((int)blockIdx.x < rs.need) round_execute<A>(a, L, rs);
+    if (!grid_barrier(a.bar, G * (unsigned long long)(k + 1), &ctl->abort, &L.misc[63])) return;
+  }
+  // every workgroup read r_cur before the first barrier
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    __hip_atomic_store(&ctl->r_cur, r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&ctl->next_need, round_state(a, r).need, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -586,7 +959,7 @@ __global__ void __launch_bounds__(1024) k_persistent(RoundArgs a) {
 
 size_t trs_round_lds_bytes(int block, int npt, int tab_words, int n_rules) {
   size_t words = (size_t)((tab_words + 3) & ~3) + (size_t)block * npt +
-                 (size_t)DBUF_PER_THREAD * block + 64 + (size_t)n_rules;
+                 (size_t)3 * QBUF_PER_THREAD * block + 64 + (size_t)n_rules;
   return words * sizeof(int32_t);
 }
 
@@ -635,11 +1008,6 @@ hipError_t trs_prepare_kernels(int A, size_t lds) {
 hipError_t trs_launch_round(int A, const RoundArgs &a, int grid, int block, hipStream_t s) {
   const size_t lds = trs_round_lds_bytes(block, a.npt, a.tab_words, a.n_rules);
   DISPATCH_A(A, launch_round_A, a, grid, block, lds, s);
-  return hipGetLastError();
-}
-
-hipError_t trs_launch_advance(Ctl *ctl, int k, hipStream_t s) {
-  hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, ctl, k);
   return hipGetLastError();
 }
 

@@ -18,13 +18,17 @@
 // read copy nf_read of nf for this, Section 3).  Instead of copying, the
 // marker carries the parity of the round that set it:
 //   0x00          free (or never used)
-//   0x01          live, not in normal form           (ACTIVE)
+//   0x01 | m<<3   live, not in normal form           (ACTIVE); m = memo
 //   0x03 | e<<2   live, created in a round of parity e (ACTIVE|PEND)
 //   0x80          live, normal form                  (NF)
 //   0x82 | e<<2   live, became normal form in a round of parity e (NF|PEND)
 // A marker with the current parity is "not yet"; with the other parity it is
-// already valid, and the slot's own sweep rewrites it to the plain state in
-// the next round, so markers never outlive two rounds.
+// already valid, and is rewritten to the plain state in the next round (by
+// the slot's own sweep, or from the retire list when only a frontier is
+// swept), so markers never outlive two rounds.  The memo m (bits 3-5) is the
+// paper's "last subterm checked": 1 + the index of the argument that was not
+// yet a normal form when the node was last examined, so a still-blocked node
+// costs one argument read and one state read.
 #pragma once
 #include <stdint.h>
 
@@ -33,6 +37,8 @@
 #define ST_PEND 0x02u
 #define ST_EPOCH 0x04u
 #define ST_NF 0x80u
+#define ST_MEMO_SHIFT 3
+#define ST_MEMO_MASK 0x38u
 
 // ---------------------------------------------------------------- tables
 // Compiled rule tables (int32 words), loaded into LDS by every workgroup.
@@ -40,7 +46,8 @@
 //   [TAB_SYM + f]                       symbol word: arity | nrules<<8 | first<<16
 //   [TAB_SYM + n_sym + r]               word offset of rule r's program
 // Rule program at offset p:
-//   p+0  npat | nnew<<4 | var_root<<8 | root_nf<<9 | npos<<12 | nneg<<16 | rootpat<<20
+//   p+0  npat | nnew<<4 | var_root<<8 | root_nf<<9 | root_ready<<10 | npos<<12 |
+//        nneg<<16 | rootpat<<20
 //   p+1  root symbol (non-variable right-hand side) or -1
 //   p+2  offset of the root operand list      (ar(root) operand words)
 //   p+3  offset of the new-node list          (per node: header, operands)
@@ -50,7 +57,10 @@
 //                     parent | pos<<4 | is_var<<8 | sym<<16
 // Operand word: k >= 0 -> the slot matched by pattern node k (k >= 1);
 //               k <  0 -> the slot of new node (-1-k).
-// New-node header: sym | rc_init<<16 | born_nf<<24.
+// New-node header: sym | rc_init<<16 (6 bits) | born_nf<<22 | ready<<23 | referrer<<24
+// (referrer: 0 = the root, j+1 = new node j; the parent hint of the node).
+// born_nf: a constructor over normal forms; ready: not born_nf and all its
+// arguments are normal forms at birth (queued for the next round).
 // Delta word: pattern node | (delta & 0xff)<<8 (signed 8-bit delta).
 #define TAB_SYM 4
 #define TAB_MAX_WORDS 4096
@@ -61,7 +71,7 @@ static inline int32_t tab_sym_word(int32_t arity, int32_t nrules, int32_t first)
 
 // ---------------------------------------------------------------- control
 #define CTL_SPREAD 64    // statistics counters are spread over this many words
-#define CTL_NSTAT 8
+#define CTL_NSTAT 10
 enum {
   STAT_ACTIVE = 0,  // live non-normal-form slots visited
   STAT_READY,       // of those, all arguments in normal form
@@ -71,6 +81,8 @@ enum {
   STAT_FREED,       // nodes collected
   STAT_VISITS,      // slots examined
   STAT_MLP,         // predictor evaluations
+  STAT_RCOPS,       // reference-count atomics (rewrite and collection)
+  STAT_MEMO,        // active slots found still blocked by their memo argument
 };
 
 struct RoundCnt {
@@ -79,8 +91,9 @@ struct RoundCnt {
   int32_t dead;    // dead-list appends in the round
   int32_t active;  // nonzero if a live non-normal-form slot was seen
   int32_t err;     // nonzero: trs_status of a device-detected error
-  int32_t front;   // frontier appends (frontier modes)
-  int32_t pad[2];
+  int32_t front;   // appends to the next round's frontier
+  int32_t ret;     // appends to the retire list
+  int32_t full;    // the round examined every slot (full sweep)
 };
 
 struct Ctl {
@@ -92,9 +105,14 @@ struct Ctl {
   int32_t fs[3][2];    // free-stack sizes at the start of round r
   int32_t peak_n;
   int32_t gc_rounds;
-  int32_t r_base;      // round number of chunk offset 0 (advanced by the graph)
+  int32_t next_need;   // workgroups the next launch's first round uses
+  int32_t r_cur;       // next round to execute (advanced by the last workgroup)
   int32_t abort;       // set when a device-wide barrier wait timed out
-  int32_t pad[2];
+  int32_t stamp_base;  // frontier-notification stamps of this run start here
+  int32_t full_sweeps; // rounds that swept every slot
+  int32_t ticket;      // workgroups of the current launch that have finished
+  int32_t r_reached;   // round after the last one workgroup 0 ran alone
+  int32_t pad2[3];
   RoundCnt cnt[3];     // counters accumulated during round r (index r % 3)
   unsigned long long stat[CTL_NSTAT][CTL_SPREAD];
   unsigned long long rule_apps[256][4];
@@ -107,5 +125,11 @@ struct Pool {
   int32_t *rc;
   int32_t *fstack0, *fstack1;
   int32_t *dead0, *dead1;
+  // frontier modes
+  int32_t *par;             // parent hint: the slot that referenced the node
+                            // when it was created (0 for term roots)
+  int32_t *front0, *front1; // frontier of the next round (round r appends to r&1)
+  int32_t *ret0, *ret1;     // markers set in round r to retire in round r+1
+  int32_t *qstamp;          // last notification stamp (deduplicates appends)
   int64_t N;
 };

@@ -43,16 +43,28 @@ class trs_opts(ctypes.Structure):
 class trs_stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in (
         "rounds", "rule_apps", "node_visits", "active_visits", "allocs", "frees",
-        "peak_slots", "gc_rounds", "mlp_evals", "full_sweeps", "launches")] + [
+        "peak_slots", "gc_rounds", "mlp_evals", "full_sweeps", "launches", "ready_visits",
+        "nf_set", "rc_atomics", "memo_blocked")] + [
         ("device_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
 
 
+class trs_membench_result(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in (
+        "stream_read_gbps", "gather4_hbm_gops", "gather4_llc_gops", "gather1_llc_gops",
+        "atomic_random_gops", "load_latency_far_ns", "load_latency_near_ns",
+        "atomic_latency_ns", "empty_kernel_us", "clock_mhz")] + [
+        ("l2_bytes", ctypes.c_int64), ("cu_count", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_ if n != "pad"}
+
+
 EXPORTS = ["trs_create", "trs_destroy", "trs_load_rules", "trs_load_terms", "trs_normalize",
            "trs_read_nf", "trs_rule_counts", "trs_default_opts", "trs_device_bytes",
-           "trs_status_str", "trs_last_error"]
+           "trs_membench", "trs_status_str", "trs_last_error"]
 
 
 def _load_lib():
@@ -82,6 +94,8 @@ def _load_lib():
     lib.trs_default_opts.restype = None
     lib.trs_device_bytes.argtypes = [ctypes.c_int64, ctypes.c_int32]
     lib.trs_device_bytes.restype = ctypes.c_int64
+    lib.trs_membench.argtypes = [ctypes.c_int32, P(trs_membench_result)]
+    lib.trs_membench.restype = ctypes.c_int32
     lib.trs_status_str.argtypes = [ctypes.c_int32]
     lib.trs_status_str.restype = ctypes.c_char_p
     lib.trs_last_error.argtypes = [vp]
@@ -166,6 +180,14 @@ def trs_rule_counts(h, n_rules: int) -> np.ndarray:
     _check(h, _lib.trs_rule_counts(h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                                    len(out)))
     return out[:n_rules]
+
+
+def trs_membench(device: int = 0) -> dict:
+    r = trs_membench_result()
+    st = _lib.trs_membench(device, ctypes.byref(r))
+    if st != TRS_OK:
+        raise TRSError(st, "trs_membench")
+    return r.as_dict()
 
 
 def trs_device_bytes(pool_slots: int, maxarity: int) -> int:

@@ -30,65 +30,84 @@ def test_golden(path):
     assert_parity(trs, [trs.encode(ex["input"])], 1 << 12, label=os.path.basename(path))
 
 
-def test_peano_small_trees():
+MODES = {"plain": 0, "frontier": 1}
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_peano_small_trees(mode):
     trs = systems.peano()
     rng = np.random.default_rng(11)
     terms = [G.peano_tree(trs, rng, int(rng.integers(1, 300))) for _ in range(24)]
-    assert_parity(trs, terms, 1 << 18, label="peano small")
+    assert_parity(trs, terms, 1 << 18, label=f"peano small {mode}", mode=MODES[mode])
 
 
-def test_cfg0():
+@pytest.mark.parametrize("mode", MODES)
+def test_cfg0(mode):
     w = G.cfg0()
-    st = assert_parity(w.trs, w.terms, w.pool_slots, w.maxarity, label=w.name)
+    st = assert_parity(w.trs, w.terms, w.pool_slots, w.maxarity, label=f"{w.name} {mode}",
+                       mode=MODES[mode])
     v, cnt = CF.peano_eval(w.trs, w.terms[0])
     assert st["rule_apps"] == sum(cnt.values())
 
 
+@pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("n", [0, 1, 2, 3, 7, 12, 16])
-def test_fib_small(n):
+def test_fib_small(n, mode):
     trs = systems.fib()
-    assert_parity(trs, [G.g_term(trs, n)], 1 << 16, label=f"g({n})")
+    assert_parity(trs, [G.g_term(trs, n)], 1 << 16, label=f"g({n}) {mode}", mode=MODES[mode])
 
 
+@pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("n", [20, 25])
-def test_cfg1(n):
+def test_cfg1(n, mode):
     w = G.cfg1(n)
-    st = assert_parity(w.trs, w.terms, w.pool_slots, w.maxarity, label=w.name)
+    st = assert_parity(w.trs, w.terms, w.pool_slots, w.maxarity, label=f"{w.name} {mode}",
+                       mode=MODES[mode])
     assert st["rule_apps"] == sum(CF.g_counts(n).values())
 
 
-def test_msort_small_lists():
+@pytest.mark.parametrize("mode", MODES)
+def test_msort_small_lists(mode):
     trs = systems.msort()
     rng = np.random.default_rng(12)
     terms = [G.sort_term(trs, rng.integers(0, 64, size=int(rng.integers(0, 70))))
              for _ in range(16)]
-    assert_parity(trs, terms, 1 << 20, label="msort small")
+    assert_parity(trs, terms, 1 << 20, label=f"msort small {mode}", mode=MODES[mode])
 
 
-def test_cfg2():
+@pytest.mark.parametrize("mode", MODES)
+def test_cfg2(mode):
     w = G.cfg2()
-    assert_parity(w.trs, w.terms, w.pool_slots, w.maxarity, label=w.name)
+    assert_parity(w.trs, w.terms, w.pool_slots, w.maxarity, label=f"{w.name} {mode}",
+                  mode=MODES[mode])
 
 
-def test_batch_mini():
+@pytest.mark.parametrize("mode", MODES)
+def test_batch_mini(mode):
     w = G.cfg3(n_terms=96, pool_slots=1 << 22, scale="mini")
-    assert_parity(w.trs, w.terms, w.pool_slots, w.maxarity, label=w.name)
+    assert_parity(w.trs, w.terms, w.pool_slots, w.maxarity, label=f"{w.name} {mode}",
+                  mode=MODES[mode])
 
 
+@pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("block,npt", [(64, 1), (128, 2), (256, 4), (512, 8), (1024, 16)])
-def test_launch_shapes_agree(block, npt):
+def test_launch_shapes_agree(block, npt, mode):
     w = G.cfg3(n_terms=48, pool_slots=1 << 21, scale="mini")
-    assert_parity(w.trs, w.terms, w.pool_slots, w.maxarity, label=f"mini B{block} npt{npt}",
-                  block=block, nodes_per_thread=npt)
+    assert_parity(w.trs, w.terms, w.pool_slots, w.maxarity,
+                  label=f"mini B{block} npt{npt} {mode}", block=block, nodes_per_thread=npt,
+                  mode=MODES[mode])
 
 
-def test_ttree():
+@pytest.mark.parametrize("mode", MODES)
+def test_ttree(mode):
     w = G.ttree(10, pool_slots=1 << 18)
-    st = assert_parity(w.trs, w.terms, w.pool_slots, w.maxarity, label=w.name)
+    st = assert_parity(w.trs, w.terms, w.pool_slots, w.maxarity, label=f"{w.name} {mode}",
+                       mode=MODES[mode])
     assert st["rule_apps"] == CF.ttree_counts(10)
 
 
-def test_msort5_arity5():
+@pytest.mark.parametrize("mode", MODES)
+def test_msort5_arity5(mode):
     trs = systems.msort5()
     rng = np.random.default_rng(5)
 
@@ -101,7 +120,7 @@ def test_msort5_arity5():
     for _ in range(6):
         leaves = [f"Leaf(Sort({lst(rng.integers(0, 9, size=7))}))" for _ in range(4)]
         terms.append(trs.encode(f"Node(Node({leaves[0]}, {leaves[1]}), Node({leaves[2]}, {leaves[3]}))"))
-    assert_parity(trs, terms, 1 << 16, label="msort5")
+    assert_parity(trs, terms, 1 << 16, label=f"msort5 {mode}", mode=MODES[mode])
 
 
 def test_already_normal_and_empty():
@@ -129,10 +148,36 @@ def test_round_limit_reports_error():
     assert e.value.code in (T.TRS_E_ROUNDS, T.TRS_E_POOL)
 
 
-def test_persistent_kernel_agrees():
+@pytest.mark.parametrize("mode", MODES)
+def test_persistent_kernel_agrees(mode):
     w = G.cfg3(n_terms=48, pool_slots=1 << 21, scale="mini")
-    assert_parity(w.trs, w.terms, w.pool_slots, w.maxarity, label="mini persistent",
-                  persistent=1)
+    assert_parity(w.trs, w.terms, w.pool_slots, w.maxarity, label=f"mini persistent {mode}",
+                  persistent=1, mode=MODES[mode])
+
+
+def test_frontier_with_shared_redexes():
+    # a right-hand side with two equal subterms that are not normal forms:
+    # the compiled rule shares one node between two parents, so only one
+    # parent is notified when it becomes a normal form; the other must be
+    # found by a full sweep.  The normal form must not depend on that.
+    for rhs in ("p(h(X), h(X))", "p(h(X), k(h(X)))"):
+        trs = parse_trs(f"""
+sym 0/0 S/1 p/2 d/1 h/1 k/1
+var X Y
+eqn d(X) = {rhs}
+eqn h(S(X)) = S(h(X))
+eqn h(0) = 0
+eqn k(Y) = Y
+eqn p(0, Y) = Y
+eqn p(S(X), Y) = S(p(X, Y))
+""")
+        ks = (0, 1, 3, 6)
+        terms = [trs.encode("d(" + "S(" * k + "0" + ")" * k + ")") for k in ks]
+        for mode in MODES.values():
+            nfs, counts, st = run_gpu(trs, terms, 1 << 14, mode=mode)
+            say(f"[shared] {rhs} mode {mode}: full sweeps {st['full_sweeps']}")
+            for k, nf in zip(ks, nfs):
+                np.testing.assert_array_equal(nf, CF.numeral_code(trs, 2 * k))
 
 
 def test_repeat_normalize_same_context():
