@@ -8,15 +8,20 @@ the whole job (the paper's "rewritten terms per second"), with the inputs
 already in HBM when the timed region starts.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cfg3]
-                       [--mode plain|persistent] [--no-cpu-baseline]
+                       [--mode learned|plain|frontier] [--compare plain,frontier]
+                       [--weights PATH] [--no-cpu-baseline]
 
 The default workload is the batched configuration: 4096 independent terms
 (plus/times trees, g(S^n(0)) and merge sorts in equal parts) in one 2^27-slot
-pool, whose full sweeps exceed the 256 MB Infinity Cache.  The printed JSON
-line carries a ``roofline`` object for the round kernel (algorithmic bytes of
-the run / device time of the round loop, against 8 TB/s) and a
-``cpu_baseline`` object: the CPU oracle timed on a bounded sample of the same
-workload on one host core.
+pool, whose full sweeps exceed the 256 MB Infinity Cache.  The default mode
+is the learned frontier (the predictor's parameters come from --weights, or
+are trained on the device first, outside the timed region); the same
+workload is also run once in each --compare mode and reported under
+``compare`` (plain vs learned frontier).  The printed JSON line carries a
+``roofline`` object for the round kernel (algorithmic bytes of the run /
+device time of the round loop, against 8 TB/s) and a ``cpu_baseline``
+object: the CPU oracle timed on a bounded sample of the same workload on one
+host core.
 """
 
 from __future__ import annotations
@@ -57,27 +62,42 @@ def make_workload(name: str):
 
 
 def algorithmic_bytes(st: dict, A: int) -> dict:
-    """Bytes the method itself must move, from the run's counters:
-    1 B state per visited slot; per live non-normal-form slot still blocked
-    by the argument recorded at its previous examination 4 B (that argument
-    index) + 1 B (its state); per other live non-normal-form slot 4 B symbol,
-    4A B argument indices and A one-byte argument-state gathers; per ready
-    slot A 4-byte argument-symbol gathers for matching; per rule application
-    the rewritten root (4 + 4A + 1 B); per created node 4 + 4A + 4 + 1 B; per
-    reference-count atomic 8 B (read and write of a 4-byte count); per
-    collected node its symbol, arguments, state and free-list entry."""
+    """Bytes the method itself must move, from the run's counters, whatever
+    shortcut the kernel takes: 1 B state per visited slot; per live
+    non-normal-form slot 4 B symbol + 4A B argument indices + A one-byte
+    argument-state reads; per rule application A 4-byte argument-symbol reads
+    for matching and the rewritten root (4 + 4A + 1 B); per created node
+    4 + 4A + 4 + 1 B; per reference-count atomic 8 B (read and write of a
+    4-byte count); per collected node its argument indices and free-list
+    entry (its count decrements are among the atomics)."""
     parts = {
         "sweep": st["node_visits"] * 1,
-        "memo_blocked": st["memo_blocked"] * (4 + 1),
-        "active": (st["active_visits"] - st["memo_blocked"]) * (4 + 4 * A + A),
-        "match": st["ready_visits"] * 4 * A,
+        "active": st["active_visits"] * (4 + 4 * A + A),
+        "match": st["rule_apps"] * 4 * A,
         "rewrite": st["rule_apps"] * (4 + 4 * A + 1),
         "alloc": st["allocs"] * (4 + 4 * A + 4 + 1),
         "rc_atomics": st["rc_atomics"] * 8,
-        "collect": st["frees"] * (4 + 4 * A + 1 + 4),
+        "collect": st["frees"] * (4 * A + 4),
     }
     parts["total"] = sum(parts.values())
     return parts
+
+
+def load_predictor(w, path):
+    """Predictor parameters for the workload's system: from path (or the
+    packaged default), else trained on the device now from plain-run traces
+    (outside the timed region)."""
+    from paper_2009_07174_amd import predictor as PR
+    path = path or PR.DEFAULT_WEIGHTS
+    if os.path.exists(path):
+        log(f"[bench] predictor parameters from {path}")
+        return PR.load(path, w.trs.symbols)
+    log(f"[bench] no predictor at {path}: training one on the device")
+    recs = [PR.collect(trs, terms, pool, 1_000_000, log=log)
+            for _, trs, terms, pool, _ in PR.training_sets("full")]
+    import numpy as np
+    params, _ = PR.train(len(w.trs.symbols), np.concatenate(recs), log=log)
+    return params
 
 
 def cpu_baseline(w, budget_s: float = 15.0):
@@ -110,11 +130,17 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cfg3")
-    ap.add_argument("--mode", default="plain", choices=["plain", "frontier"])
+    ap.add_argument("--mode", default="learned", choices=["plain", "frontier", "learned"])
+    ap.add_argument("--compare", default="plain,frontier",
+                    help="comma-separated modes run once more for comparison ('' = none)")
+    ap.add_argument("--weights", default=None, help="predictor parameters (.npz)")
+    ap.add_argument("--threshold", type=float, default=0.1)
     ap.add_argument("--persistent", action="store_true")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--npt", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default (or given) block and nodes per thread")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); the batched "
@@ -133,9 +159,18 @@ def main():
     ctx.load_trs(w.trs)
     off, code = w.packed()
     ctx.load_terms(off, code)
-    mode = {"plain": T.TRS_MODE_PLAIN, "frontier": T.TRS_MODE_FRONTIER}[args.mode]
-    opts = T.Options(block=args.block, nodes_per_thread=args.npt, mode=mode,
-                     persistent=1 if args.persistent else 0)
+    MODES = {"plain": T.TRS_MODE_PLAIN, "frontier": T.TRS_MODE_FRONTIER,
+             "learned": T.TRS_MODE_LEARNED}
+    compare = [m for m in args.compare.split(",") if m and m != args.mode]
+    if args.mode == "learned" or "learned" in compare:
+        ctx.set_predictor(load_predictor(w, args.weights))
+    opts = T.Options(block=args.block, nodes_per_thread=args.npt, mode=MODES[args.mode],
+                     persistent=1 if args.persistent else 0, threshold=args.threshold)
+    tune = None
+    if not args.no_autotune and not args.block and not args.npt:
+        log("[bench] autotuning block and nodes per thread")
+        opts, tune = ctx.autotune(opts)
+        log(f"[bench] autotune: {tune}")
     stream = torch.cuda.current_stream()
     for i in range(args.warmup):
         st = ctx.normalize(opts)
@@ -183,7 +218,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "terms": w.n_terms, "initial_nodes": w.initial_nodes,
                    "pool_slots": w.pool_slots, "maxarity": A, "mode": args.mode,
-                   "persistent": bool(args.persistent)},
+                   "persistent": bool(args.persistent), "block": opts.block,
+                   "nodes_per_thread": opts.nodes_per_thread},
+        "autotune": tune,
         "rule_apps": apps,
         "node_visits_per_s": st["node_visits"] * args.steps / wall,
         "rounds": rounds,
@@ -200,6 +237,25 @@ def main():
                      "avg_launch_us": 1e3 * ev_ms_step / max(st["launches"], 1)},
         "stats": st,
     }
+    if compare:
+        res["compare"] = {}
+        for m in compare:
+            o = T.Options(block=opts.block, nodes_per_thread=opts.nodes_per_thread, mode=MODES[m],
+                          persistent=1 if args.persistent else 0, threshold=args.threshold)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            sm = ctx.normalize(o)
+            torch.cuda.synchronize()
+            wm = time.perf_counter() - t1
+            log(f"[bench] compare {m}: {sm['rounds']} rounds, {sm['device_ms']:.1f} ms")
+            if sm["rule_apps"] != apps:
+                raise SystemExit(f"compare {m}: {sm['rule_apps']} rule applications, "
+                                 f"expected {apps}")
+            res["compare"][m] = {
+                "value": sm["rule_apps"] / wm, "ms_per_step": 1e3 * wm, "rounds": sm["rounds"],
+                "node_visits": sm["node_visits"], "node_visits_per_s": sm["node_visits"] / wm,
+                "full_sweeps": sm["full_sweeps"], "speedup_of_" + args.mode: wm / (wall / args.steps),
+                "algorithmic_gbps": algorithmic_bytes(sm, A)["total"] / wm / 1e9}
     if not args.no_cpu_baseline:
         log("[bench] CPU baseline (oracle, one core)")
         res["cpu_baseline"] = cpu_baseline(w)

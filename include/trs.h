@@ -84,7 +84,9 @@ typedef struct {
 #define TRS_MODE_PLAIN 0     /* full sweep of every slot every round */
 #define TRS_MODE_FRONTIER 1  /* sweep a compacted frontier; full confirmation
                                 sweep before declaring a normal form */
-#define TRS_MODE_LEARNED 2   /* frontier filtered by the trained MLP */
+#define TRS_MODE_LEARNED 2   /* frontier chosen by the trained predictor (below)
+                                instead of parent notification; full
+                                confirmation sweep as in TRS_MODE_FRONTIER */
 
 typedef struct {
   int32_t mode;              /* TRS_MODE_* */
@@ -99,8 +101,11 @@ typedef struct {
   int32_t persistent;        /* 1 = one cooperative persistent kernel runs the
                                 rounds with device-wide barriers; 0 = one
                                 launch per round (captured in a HIP graph) */
-  int32_t trace;             /* 1 = log per-(node, round) feature records
-                                (for training the frontier predictor) */
+  int32_t trace;             /* plain mode: 0 = off; k in 1..65536 = log a
+                                record for a blocked node-round with
+                                probability k/65536 (for training the
+                                predictor; the memo shortcut is off then) */
+  int64_t trace_cap;         /* records kept (0 = 1<<24); later ones dropped */
 } trs_opts;
 
 typedef struct {
@@ -120,6 +125,8 @@ typedef struct {
   int64_t rc_atomics;    /* reference-count atomic operations */
   int64_t memo_blocked;  /* active slots found still blocked by the argument
                             recorded at their previous examination */
+  int64_t mlp_kept;      /* learned mode: predictor decisions that kept the node */
+  int64_t trace_records; /* trace records logged (may exceed trace_cap) */
   double device_ms;      /* device time of the round loop (HIP events) */
 } trs_stats;
 
@@ -164,6 +171,26 @@ int64_t trs_device_bytes(int64_t pool_slots, int32_t maxarity);
 /* Default options (mode plain, tuned block and nodes per thread). */
 void trs_default_opts(trs_opts *opts);
 
+/* Autotuner of the launch shape (the batching step: block size and nodes per
+ * thread).  Times trs_normalize of the loaded terms under *base, first over
+ * block sizes 128, 256, 512, 1024 at 16 nodes per thread, then over 4 and 8
+ * nodes per thread at the best block (six complete normalisations).  *best
+ * receives *base with the fastest block and nodes_per_thread.  The result is cached per context and loaded terms (a
+ * second call with the same mode returns it without trials; res->trials = 0
+ * then).  After the call the context holds a completed normalisation. */
+typedef struct {
+  int32_t trials;       /* configurations timed by this call */
+  int32_t best_block;
+  int32_t best_npt;
+  int32_t pad;
+  double best_ms;       /* device time of the fastest trial */
+  int32_t block[8], npt[8];
+  double ms[8];         /* device time per trial */
+} trs_tune_result;
+
+trs_status trs_autotune(trs_ctx *ctx, const trs_opts *base, trs_opts *best,
+                        trs_tune_result *res);
+
 /* Memory microbenchmarks of a device: the paper's comparison of aligned and
  * random-access bandwidth (Section 4, hardware table), re-measured on this
  * GPU, plus the latencies that bound one rewrite round.  Allocates and frees
@@ -174,10 +201,13 @@ typedef struct {
   double gather4_llc_gops;      /* random 4-byte reads over 64 MiB, 1e9/s */
   double gather1_llc_gops;      /* random 1-byte reads over 64 MiB, 1e9/s */
   double atomic_random_gops;    /* random non-returning atomic adds, 1e9/s */
-  double load_latency_far_ns;   /* dependent load, 512 MiB random cycle */
+  double load_latency_far_ns;   /* dependent load, 512 MiB random cycle (one
+                                   wave, 64 independent chains) */
   double load_latency_near_ns;  /* dependent load, 256 KiB random cycle */
-  double atomic_latency_ns;     /* dependent returning atomic */
+  double atomic_latency_ns;     /* dependent returning atomic (64 chains) */
   double empty_kernel_us;       /* back-to-back launch of an empty kernel */
+  double copy_gbps;             /* plain device copy (bytes read + written) */
+  int64_t copy_bytes;           /* bytes that copy read (and wrote) per launch */
   double clock_mhz;
   int64_t l2_bytes;
   int32_t cu_count;
@@ -185,6 +215,87 @@ typedef struct {
 } trs_membench_result;
 
 trs_status trs_membench(int32_t device, trs_membench_result *out);
+
+/* ------------------------------------------------------------------------
+ * Frontier predictor (TRS_MODE_LEARNED).  Not part of the paper: a small
+ * network that predicts, for a node found blocked in a round (an argument
+ * not yet a normal form), whether it will be able to fire or become a normal
+ * form in the next round; only nodes it keeps are examined then, and a full
+ * sweep still confirms the normal form (so results stay exact).
+ *
+ *   x  = [E[sym] (16), arity/8, c_0..c_4, bucket(age)/15, 0]       (24)
+ *   h1 = relu(W1 x + b1) (32);  h2 = relu(W2 h1 + b2) (32)
+ *   p  = sigmoid(w3 . h2 + b3)
+ *
+ * c_j = 1 when argument j is a normal form or j >= arity; age = rounds since
+ * the node last changed, bucket(0) = 0, bucket(a) = min(15, floor(log2 a)+1).
+ * Parameters are bfloat16 (uint16 bit patterns), concatenated in the order
+ * E[n_sym][16], W1[32][24], b1[32], W2[32][32], b2[32], w3[32], b3[1]
+ * (row-major); arithmetic accumulates in float32.
+ *
+ * Trace record (uint64, written by trs_normalize with trs_opts.trace > 0):
+ * sym bits 0-15, arity 16-19, c_0..c_4 bits 20-24, age bucket 25-28, label
+ * bit 32 (1: the node fired or became a normal form in the next round).
+ * ------------------------------------------------------------------------ */
+#define TRS_MLP_EMB 16
+#define TRS_MLP_DIN 24
+#define TRS_MLP_H 32
+#define TRS_MLP_MAX_SYM 256   /* learned mode keeps the decision table in LDS */
+
+/* Number of bfloat16 parameters for n_sym symbols; -1 if n_sym is outside
+ * 1..TRS_MLP_MAX_SYM. */
+int64_t trs_mlp_param_count(int32_t n_sym);
+
+/* Forward (and backward) pass on device `device` over n records (host
+ * arrays, copied in): mean binary cross-entropy in *loss_out; if grads_out is
+ * not NULL, the gradient of that mean with respect to every parameter
+ * (float32, parameter order above); if probs_out is not NULL, p per record.
+ * TRS_E_ARG on null inputs, n <= 0 or a record whose symbol is >= n_sym. */
+trs_status trs_mlp_eval(int32_t device, int32_t n_sym, const uint16_t *params_bf16, int64_t n,
+                        const uint64_t *records, double *loss_out, float *grads_out,
+                        float *probs_out);
+
+typedef struct {
+  int32_t epochs;   /* passes over the training part, 1..64 */
+  int32_t batch;    /* records per Adam step, >= 64 */
+  float lr;         /* Adam step size (beta1 0.9, beta2 0.999, eps 1e-8) */
+  float val_frac;   /* trailing fraction of the records held out, [0, 1) */
+} trs_train_opts;
+
+typedef struct {
+  int32_t epochs_run;
+  int32_t pad;
+  float train_loss[64];  /* mean loss over each epoch's steps */
+  float val_loss[64];    /* loss on the held-out records after each epoch */
+  double device_ms;      /* device time of the whole training */
+} trs_train_result;
+
+/* Train the predictor on the device with Adam on float32 master weights
+ * (rounded to bfloat16 after every step) from init_bf16; the records are
+ * used in the given order (shuffle them first).  Writes the trained
+ * parameters to params_out. */
+trs_status trs_mlp_train(int32_t device, int32_t n_sym, int64_t n, const uint64_t *records,
+                         const trs_train_opts *opts, const uint16_t *init_bf16,
+                         uint16_t *params_out, trs_train_result *result);
+
+/* The predictor evaluated on the device for every input it can see:
+ * probs_out[(sym * 32 + c) * 16 + bucket] (n_sym * 512 floats, may be NULL)
+ * and the keep decisions p >= threshold as a bit table words_out (n_sym * 16
+ * uint32; bit i of word i/32; may be NULL).  arity[sym] gives the arity fed
+ * to the network. */
+trs_status trs_mlp_table(int32_t device, int32_t n_sym, const int32_t *arity,
+                         const uint16_t *params_bf16, float threshold, float *probs_out,
+                         uint32_t *words_out);
+
+/* Install predictor parameters in a context (copied; n_params must equal
+ * trs_mlp_param_count of the loaded system).  Required before a
+ * TRS_MODE_LEARNED trs_normalize. */
+trs_status trs_set_predictor(trs_ctx *ctx, const uint16_t *params_bf16, int64_t n_params);
+
+/* Trace records of the last trs_normalize run with trs_opts.trace > 0, in
+ * the order they were logged (labels complete).  With buf == NULL only
+ * *n_out is set; otherwise min(cap, count) records are copied. */
+trs_status trs_read_trace(trs_ctx *ctx, uint64_t *buf, int64_t cap, int64_t *n_out);
 
 const char *trs_status_str(trs_status s);
 const char *trs_last_error(trs_ctx *ctx);

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtrs.so")
-SOURCES = ["trs_host.cpp", "trs_kernels.hip", "trs_membench.hip"]
+SOURCES = ["trs_host.cpp", "trs_kernels.hip", "trs_mlp.hip", "trs_membench.hip"]
 ARCH = os.environ.get("TRS_OFFLOAD_ARCH", "gfx950")
 
 # packed FP32 instructions are kept out of every HIP code object

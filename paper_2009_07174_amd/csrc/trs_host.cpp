@@ -5,15 +5,18 @@
 #include <algorithm>
 #include <chrono>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 #include <map>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "trs.h"
 #include "trs_kernels.h"
 #include "trs_layout.h"
+#include "trs_mlp.h"
 
 namespace {
 
@@ -67,8 +70,22 @@ struct trs_ctx {
   // captured chunk of rounds (one launch per round)
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
-  int g_grid = 0, g_block = 0, g_npt = 0, g_k = 0, g_mode = -1, g_cont = 0;
+  int g_grid = 0, g_block = 0, g_k = 0;
   size_t g_lds = 0;
+  RoundArgs g_args;  // kernel arguments baked into the captured chunk
+
+  // frontier predictor (learned mode) and tracing
+  std::vector<uint16_t> pred;  // installed parameters (empty: none)
+  bool pred_dirty = false;
+  uint16_t *d_pred = nullptr;
+  int32_t *d_arity = nullptr;
+  float *d_pprobs = nullptr, *d_ploss = nullptr;
+  uint64_t *d_prec = nullptr;
+  unsigned long long *d_trace_rec = nullptr;
+  int32_t *d_trace_n = nullptr;
+  int64_t trace_alloc = 0, trace_count = 0;
+  // autotuner results for the loaded terms, per mode: block, npt, ms
+  std::map<int, std::tuple<int, int, double>> tuned;
 
   // results of the last normalisation
   bool normalized = false;
@@ -345,7 +362,7 @@ std::vector<Piece> device_pieces(trs_ctx *c, int64_t N, int A) {
       {(void **)&c->pool.dead0, (size_t)N * 4},
       {(void **)&c->pool.dead1, (size_t)N * 4},
       {(void **)&c->d_ctl, sizeof(Ctl)},
-      {(void **)&c->d_tab, (size_t)TAB_MAX_WORDS * 4},
+      {(void **)&c->d_tab, (size_t)(TAB_MAX_WORDS + TAB_GATE_MAX_WORDS) * 4},
       {(void **)&c->d_bar, 256},
       {(void **)&c->d_img_hss, (size_t)N * 4},
       {(void **)&c->d_img_args, (size_t)N * A * 4},
@@ -358,6 +375,7 @@ std::vector<Piece> device_pieces(trs_ctx *c, int64_t N, int A) {
       {(void **)&c->pool.ret0, (size_t)N * 4},
       {(void **)&c->pool.ret1, (size_t)N * 4},
       {(void **)&c->pool.qstamp, (size_t)N * 4},
+      {(void **)&c->pool.wake, (size_t)N + state_pad},
   };
 }
 
@@ -447,6 +465,7 @@ void trs_default_opts(trs_opts *o) {
   o->threshold = 0.1f;
   o->persistent = 0;
   o->trace = 0;
+  o->trace_cap = 0;
 }
 
 trs_status trs_create(trs_ctx **out, const trs_config *cfg) {
@@ -485,6 +504,7 @@ trs_status trs_load_rules(trs_ctx *c, int32_t n_sym, const int32_t *arity, int32
       n_rules > TRS_MAX_RULES || (n_rules > 0 && (!rule_off || !rule_code)) || code_len < 0)
     return c->fail(TRS_E_ARG, "bad sizes or null pointers");
   c->rules_loaded = c->terms_loaded = c->normalized = false;
+  c->pred.clear();  // predictor parameters belong to a symbol set
   std::vector<int32_t> ar(arity, arity + n_sym);
   int maxar = 0;
   for (int i = 0; i < n_sym; i++) {
@@ -638,6 +658,7 @@ trs_status trs_load_terms(trs_ctx *c, int32_t n_terms, const int64_t *term_off,
   c->n_terms = n_terms;
   c->terms_loaded = true;
   c->img_on_device = false;
+  c->tuned.clear();
   return TRS_OK;
 }
 
@@ -649,8 +670,19 @@ trs_status trs_normalize(trs_ctx *c, const trs_opts *opts_in, trs_stats *stats) 
     o = *opts_in;
   else
     trs_default_opts(&o);
-  if (o.mode != TRS_MODE_PLAIN && o.mode != TRS_MODE_FRONTIER)
-    return c->fail(TRS_E_ARG, "mode not available");
+  if (o.mode != TRS_MODE_PLAIN && o.mode != TRS_MODE_FRONTIER && o.mode != TRS_MODE_LEARNED)
+    return c->fail(TRS_E_ARG, "unknown mode");
+  if (o.mode == TRS_MODE_LEARNED) {
+    if (c->pred.empty()) return c->fail(TRS_E_STATE, "learned mode needs trs_set_predictor");
+    if (!(o.threshold >= 0.f && o.threshold <= 1.f))
+      return c->fail(TRS_E_ARG, "threshold must be in [0, 1]");
+  }
+  if (o.trace < 0 || o.trace > 65536) return c->fail(TRS_E_ARG, "trace rate must be 0..65536");
+  if (o.trace && o.mode != TRS_MODE_PLAIN)
+    return c->fail(TRS_E_ARG, "traces are logged by plain-mode runs");
+  const int64_t tcap = o.trace_cap ? o.trace_cap : ((int64_t)1 << 24);
+  if (o.trace && (tcap <= 0 || tcap > INT32_MAX))
+    return c->fail(TRS_E_ARG, "trace_cap must be 1..2^31-1");
   const int B = o.block ? o.block : default_block();
   const int npt = o.nodes_per_thread ? o.nodes_per_thread : default_npt();
   if (B < 64 || B > 1024 || (B & 63)) return c->fail(TRS_E_ARG, "block must be 64..1024, /64");
@@ -679,6 +711,8 @@ trs_status trs_normalize(trs_ctx *c, const trs_opts *opts_in, trs_stats *stats) 
   HIPCHK(c, hipMemcpyAsync(c->pool.rc, c->d_img_rc, M1 * 4, hipMemcpyDeviceToDevice, s));
   HIPCHK(c, hipMemcpyAsync(c->pool.state, c->d_img_state, M1, hipMemcpyDeviceToDevice, s));
   HIPCHK(c, hipMemcpyAsync(c->pool.par, c->d_img_par, M1 * 4, hipMemcpyDeviceToDevice, s));
+  if (o.mode == TRS_MODE_PLAIN)
+    HIPCHK(c, hipMemsetAsync(c->pool.wake, 0, (size_t)c->cfg.pool_slots, s));
   HIPCHK(c, hipMemcpyAsync(c->d_tab, c->tab.data(), c->tab.size() * 4, hipMemcpyHostToDevice, s));
   std::memset(c->h_ctl, 0, sizeof(Ctl));
   c->h_ctl->n[0] = (int32_t)M1;
@@ -695,22 +729,108 @@ trs_status trs_normalize(trs_ctx *c, const trs_opts *opts_in, trs_stats *stats) 
     // per tile (one in all when a single tile covers the pool)
     const int64_t tiles = (M1 + (int64_t)B * npt - 1) / ((int64_t)B * npt);
     c->h_ctl->next_need = (int32_t)std::max<int64_t>(1, tiles);
+    // the state of round 0 as the first launch reads it: done, r, need, n,
+    // free-stack sizes, list lengths and flags (all zero but need and n)
+    c->h_ctl->pub[2] = c->h_ctl->next_need;
+    c->h_ctl->pub[3] = (int32_t)M1;
   }
   HIPCHK(c, hipMemcpyAsync(c->d_ctl, c->h_ctl, sizeof(Ctl), hipMemcpyHostToDevice, s));
   unsigned long long zero = 0;
   HIPCHK(c, hipMemcpyAsync(c->d_bar, &zero, sizeof(zero), hipMemcpyHostToDevice, s));
   HIPCHK(c, hipStreamSynchronize(s));
 
-  RoundArgs ra{};
+  // learned mode and tracing: per-slot round of the last change (initial
+  // nodes: round 0), trace buffer and the per-slot reference to the latest
+  // record (all ones: none)
+  const bool track = o.mode == TRS_MODE_LEARNED || o.trace;
+  if (track && !c->pool.lastchg) {
+    HIPCHK(c, hipMalloc(&c->pool.lastchg, (size_t)c->cfg.pool_slots * 4));
+    c->owned.push_back(c->pool.lastchg);
+  }
+  if (track) HIPCHK(c, hipMemsetAsync(c->pool.lastchg, 0, (size_t)M1 * 4, s));
+  if (o.trace) {
+    if (!c->pool.tref) {
+      HIPCHK(c, hipMalloc(&c->pool.tref, (size_t)c->cfg.pool_slots * 8));
+      c->owned.push_back(c->pool.tref);
+      HIPCHK(c, hipMalloc(&c->d_trace_n, 256));
+      c->owned.push_back(c->d_trace_n);
+    }
+    if (tcap > c->trace_alloc) {
+      if (c->d_trace_rec) {
+        HIPCHK(c, hipStreamSynchronize(s));
+        HIPCHK(c, hipFree(c->d_trace_rec));
+        c->owned.erase(std::find(c->owned.begin(), c->owned.end(), (void *)c->d_trace_rec));
+        c->d_trace_rec = nullptr;
+        c->trace_alloc = 0;
+      }
+      HIPCHK(c, hipMalloc(&c->d_trace_rec, (size_t)tcap * 8));
+      c->owned.push_back(c->d_trace_rec);
+      c->trace_alloc = tcap;
+    }
+    HIPCHK(c, hipMemsetAsync(c->pool.tref, 0xff, (size_t)c->cfg.pool_slots * 8, s));
+    HIPCHK(c, hipMemsetAsync(c->d_trace_n, 0, 4, s));
+  }
+  c->trace_count = 0;
+  int32_t gate_off = 0, gate_words = 0;
+  if (o.mode == TRS_MODE_LEARNED) {
+    // the predictor's decision table, evaluated on the device for every
+    // input, goes right after the rule tables
+    if (!c->d_pred) {
+      const size_t P = (size_t)TRS_MLP_MAX_SYM * TRS_MLP_EMB + 4096;
+      HIPCHK(c, hipMalloc(&c->d_pred, P * 2));
+      HIPCHK(c, hipMalloc(&c->d_arity, TRS_MLP_MAX_SYM * 4));
+      HIPCHK(c, hipMalloc(&c->d_pprobs, (size_t)TRS_MLP_MAX_SYM * 512 * 4));
+      HIPCHK(c, hipMalloc(&c->d_prec, (size_t)TRS_MLP_MAX_SYM * 512 * 8));
+      HIPCHK(c, hipMalloc(&c->d_ploss, 256));
+      for (void *q : {(void *)c->d_pred, (void *)c->d_arity, (void *)c->d_pprobs,
+                      (void *)c->d_prec, (void *)c->d_ploss})
+        c->owned.push_back(q);
+      c->pred_dirty = true;
+    }
+    if (c->pred_dirty) {
+      HIPCHK(c, hipMemcpyAsync(c->d_pred, c->pred.data(), c->pred.size() * 2,
+                               hipMemcpyHostToDevice, s));
+      HIPCHK(c, hipMemcpyAsync(c->d_arity, c->arity.data(), c->n_sym * 4,
+                               hipMemcpyHostToDevice, s));
+      HIPCHK(c, hipStreamSynchronize(s));  // the host vectors may change later
+      c->pred_dirty = false;
+    }
+    gate_off = (int32_t)((c->tab.size() + 3) & ~(size_t)3);
+    gate_words = c->n_sym * 16;
+    HIPCHK(c, trs_mlp_build_table(c->d_pred, c->n_sym, c->d_arity, o.threshold, c->d_pprobs,
+                                  c->d_prec, c->d_ploss, (uint32_t *)(c->d_tab + gate_off), s));
+  }
+
+  RoundArgs ra;
+  std::memset(&ra, 0, sizeof(ra));  // compared byte-wise with the captured arguments
   ra.p = c->pool;
   ra.ctl = c->d_ctl;
   ra.tab = c->d_tab;
-  ra.tab_words = (int32_t)c->tab.size();
+  ra.tab_words = gate_words ? gate_off + gate_words : (int32_t)c->tab.size();
+  ra.gate_off = gate_off;
+  ra.use_memo = (o.mode != TRS_MODE_LEARNED && !o.trace) ? 1 : 0;
+  if (o.trace) {
+    ra.trace_rate = (uint32_t)o.trace;
+    ra.trace_cap_rec = tcap;
+    ra.trace_rec = c->d_trace_rec;
+    ra.trace_n = c->d_trace_n;
+  }
   ra.n_sym = c->n_sym;
   ra.n_rules = c->n_rules;
   ra.npt = npt;
   ra.bar = c->d_bar;
   ra.mode = o.mode;
+  // opt-in phase trace of workgroup 0 (TRS_PHASE_TRACE=path: the first
+  // rounds' timestamps are written there as text after the run)
+  const char *trace_path = std::getenv("TRS_PHASE_TRACE");
+  long long *d_trace = nullptr;
+  const int trace_cap = 4096;
+  if (trace_path) {
+    HIPCHK(c, hipMalloc(&d_trace, (size_t)trace_cap * TRACE_FIELDS * 8));
+    HIPCHK(c, hipMemsetAsync(d_trace, 0, (size_t)trace_cap * TRACE_FIELDS * 8, s));
+    ra.trace = d_trace;
+    ra.trace_cap = trace_cap;
+  }
   const size_t lds = trs_round_lds_bytes(B, npt, ra.tab_words, c->n_rules);
   if (lds > 160 * 1024) return c->fail(TRS_E_ARG, "configuration needs too much LDS");
   const int TILE = B * npt;
@@ -761,8 +881,8 @@ trs_status trs_normalize(trs_ctx *c, const trs_opts *opts_in, trs_stats *stats) 
         launches++;
       }
     } else {
-      if (!c->gexec || c->g_grid != g || c->g_block != B || c->g_npt != npt || c->g_k != K ||
-          c->g_lds != lds || c->g_mode != o.mode || c->g_cont != ra.cont_rounds) {
+      if (!c->gexec || c->g_grid != g || c->g_block != B || c->g_k != K || c->g_lds != lds ||
+          std::memcmp(&c->g_args, &ra, sizeof(ra)) != 0) {
         if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
         if (c->graph) (void)hipGraphDestroy(c->graph);
         c->gexec = nullptr;
@@ -780,11 +900,9 @@ trs_status trs_normalize(trs_ctx *c, const trs_opts *opts_in, trs_stats *stats) 
         HIPCHK(c, hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
         c->g_grid = g;
         c->g_block = B;
-        c->g_npt = npt;
         c->g_k = K;
         c->g_lds = lds;
-        c->g_mode = o.mode;
-        c->g_cont = ra.cont_rounds;
+        std::memcpy(&c->g_args, &ra, sizeof(ra));
       }
       for (int i = 0; i < P; i++) {
         HIPCHK(c, hipGraphLaunch(c->gexec, s));
@@ -815,8 +933,26 @@ trs_status trs_normalize(trs_ctx *c, const trs_opts *opts_in, trs_stats *stats) 
   HIPCHK(c, hipStreamSynchronize(s));
   float ms = 0.f;
   HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+  if (d_trace) {
+    std::vector<long long> t((size_t)trace_cap * TRACE_FIELDS);
+    HIPCHK(c, hipMemcpy(t.data(), d_trace, t.size() * 8, hipMemcpyDeviceToHost));
+    (void)hipFree(d_trace);
+    if (FILE *f = std::fopen(trace_path, "w")) {
+      for (int i = 0; i < trace_cap; i++) {
+        std::fprintf(f, "%d", i);
+        for (int j = 0; j < TRACE_FIELDS; j++) std::fprintf(f, " %lld", t[(size_t)i * TRACE_FIELDS + j]);
+        std::fprintf(f, "\n");
+      }
+      std::fclose(f);
+    }
+  }
   const Ctl &h = *c->h_ctl;
   c->stamp_base += (int32_t)std::min<int64_t>(r + 2, 1 << 30);
+  if (o.trace) {
+    int32_t nt = 0;
+    HIPCHK(c, hipMemcpy(&nt, c->d_trace_n, 4, hipMemcpyDeviceToHost));
+    c->trace_count = std::min<int64_t>(nt, tcap);
+  }
   if (result == TRS_OK && h.err) {
     result = c->fail(h.err, h.err == TRS_E_POOL ? "node pool exhausted during rewriting"
                                                 : "device reported an inconsistency");
@@ -848,6 +984,8 @@ trs_status trs_normalize(trs_ctx *c, const trs_opts *opts_in, trs_stats *stats) 
     stats->nf_set = sum(STAT_NFSET);
     stats->rc_atomics = sum(STAT_RCOPS);
     stats->memo_blocked = sum(STAT_MEMO);
+    stats->mlp_kept = sum(STAT_KEEP);
+    stats->trace_records = sum(STAT_TRACE);
     stats->device_ms = ms;
   }
   if (result != TRS_OK) return result;
@@ -891,6 +1029,89 @@ trs_status trs_read_nf(trs_ctx *c, int32_t term_id, int32_t *buf, int64_t cap, i
     for (int j = c->arity[s] - 1; j >= 0; j--) stk.push_back(c->c_args[(size_t)x * A + j]);
   }
   *len_out = len;
+  return TRS_OK;
+}
+
+trs_status trs_autotune(trs_ctx *c, const trs_opts *base, trs_opts *best, trs_tune_result *res) {
+  if (!c || !base || !best) return TRS_E_ARG;
+  if (!c->terms_loaded) return c->fail(TRS_E_STATE, "load rules and terms first");
+  trs_tune_result r;
+  std::memset(&r, 0, sizeof(r));
+  auto it = c->tuned.find(base->mode);
+  if (it != c->tuned.end()) {
+    *best = *base;
+    best->block = std::get<0>(it->second);
+    best->nodes_per_thread = std::get<1>(it->second);
+    r.best_block = best->block;
+    r.best_npt = best->nodes_per_thread;
+    r.best_ms = std::get<2>(it->second);
+    if (res) *res = r;
+    return TRS_OK;
+  }
+  int bb = 0, bn = 16;
+  double bms = 0;
+  auto trial = [&](int B, int npt) -> trs_status {
+    trs_opts o = *base;
+    o.block = B;
+    o.nodes_per_thread = npt;
+    trs_stats st;
+    const trs_status s = trs_normalize(c, &o, &st);
+    if (s != TRS_OK) return s;
+    const int k = r.trials++;
+    r.block[k] = B;
+    r.npt[k] = npt;
+    r.ms[k] = st.device_ms;
+    if (bb == 0 || st.device_ms < bms) {
+      bb = B;
+      bn = npt;
+      bms = st.device_ms;
+    }
+    return TRS_OK;
+  };
+  for (int B : {128, 256, 512, 1024}) {
+    const trs_status s = trial(B, 16);
+    if (s != TRS_OK) return s;
+  }
+  const int B0 = bb;
+  for (int npt : {4, 8}) {
+    const trs_status s = trial(B0, npt);
+    if (s != TRS_OK) return s;
+  }
+  c->tuned[base->mode] = std::make_tuple(bb, bn, bms);
+  *best = *base;
+  best->block = bb;
+  best->nodes_per_thread = bn;
+  r.best_block = bb;
+  r.best_npt = bn;
+  r.best_ms = bms;
+  if (res) *res = r;
+  return TRS_OK;
+}
+
+trs_status trs_set_predictor(trs_ctx *c, const uint16_t *params_bf16, int64_t n_params) {
+  if (!c || !params_bf16) return TRS_E_ARG;
+  if (!c->rules_loaded) return c->fail(TRS_E_STATE, "load rules first");
+  const int64_t P = trs_mlp_param_count(c->n_sym);
+  if (P < 0) return c->fail(TRS_E_LIMIT, "learned mode supports at most 256 symbols");
+  if (n_params != P) return c->fail(TRS_E_ARG, "parameter count does not match the system");
+  c->pred.assign(params_bf16, params_bf16 + P);
+  c->pred_dirty = true;
+  return TRS_OK;
+}
+
+trs_status trs_read_trace(trs_ctx *c, uint64_t *buf, int64_t cap, int64_t *n_out) {
+  if (!c || !n_out) return TRS_E_ARG;
+  if (!c->normalized) return c->fail(TRS_E_STATE, "normalize first");
+  const int64_t n = c->trace_count;
+  if (!buf) {
+    *n_out = n;
+    return TRS_OK;
+  }
+  if (cap < 0) return c->fail(TRS_E_ARG, "negative capacity");
+  const int64_t k = std::min(n, cap);
+  if (k > 0)
+    HIPCHK(c, hipMemcpy(buf, c->d_trace_rec, (size_t)k * 8, hipMemcpyDeviceToHost));
+  *n_out = k;
   return TRS_OK;
 }
 

@@ -16,9 +16,26 @@ struct RoundArgs {
   int32_t nrounds;      // rounds a persistent launch may run
   int32_t cont_rounds;  // rounds workgroup 0 may continue alone in one launch
   int32_t small_cap;    // list items one workgroup takes on alone
-  int32_t mode;         // 0 full sweeps, 1 frontier (full sweep when it is empty)
+  int32_t mode;         // 0 full sweeps, 1 frontier by parent notification,
+                        // 2 frontier chosen by the predictor (full sweep when
+                        // the frontier is empty)
+  int32_t use_memo;     // memo shortcut on (off in learned mode and tracing)
+  int32_t gate_off;     // learned mode: word offset of the decision table in tab
+  uint32_t trace_rate;  // tracing: keep a blocked node-round when its hash
+                        // (16 bits) is below this; 0 = off
+  int64_t trace_cap_rec;     // records the buffer holds
+  unsigned long long *trace_rec;  // trace records
+  int32_t *trace_n;     // records logged so far
   unsigned long long *bar;  // grid barrier counter (persistent kernel)
+  long long *trace;     // optional phase timestamps of workgroup 0 (null: off)
+  int32_t trace_cap;    // rounds the trace holds (TRACE_FIELDS words each)
 };
+
+// Phase timestamps (clock64) recorded by thread 0 of workgroup 0 per round:
+// prepare start, prepare end, bookkeeping end, list phase end, sweep end,
+// statistics end, and inside the first list pass: readiness checked,
+// matched, reserved, instantiated, flushed.
+#define TRACE_FIELDS 12
 
 // LDS bytes a round kernel needs for this configuration.
 size_t trs_round_lds_bytes(int block, int npt, int tab_words, int n_rules);

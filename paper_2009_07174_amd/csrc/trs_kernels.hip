@@ -60,6 +60,34 @@ __device__ __forceinline__ int ld(const int32_t *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// 32-bit integer hash (multiply / xor-shift), used to sample trace records
+__device__ __forceinline__ uint32_t mix32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352dU;
+  x ^= x >> 15;
+  x *= 0x846ca68bU;
+  x ^= x >> 16;
+  return x;
+}
+
+// sum over the active lanes of a wave (device-library reduction)
+__device__ __forceinline__ int wave_sum(int x) { return __ockl_wfred_add_i32(x); }
+
+// Wave-aggregated reservation on a counter: lanes with pred get distinct
+// positions (others -1) and the wave issues a single atomic, where lanes
+// adding to one LDS address one by one would be serialised.  Must be called
+// by all 64 lanes of the wave (the masks come from ballots of pred, never
+// from the set of active lanes).
+__device__ __forceinline__ int wave_reserve(bool pred, int32_t *ctr) {
+  const unsigned long long m = __ballot(pred);
+  if (m == 0) return -1;
+  const int leader = __ffsll((long long)m) - 1;
+  int base = 0;
+  if (lane() == leader) base = atomicAdd(ctr, __popcll(m));
+  base = __shfl(base, leader, 64);
+  return pred ? base + __popcll(m & __lanemask_lt()) : -1;
+}
+
 // inclusive prefix sum over the 64 lanes of a wave
 __device__ __forceinline__ int wave_incl_scan(int x) {
 #pragma unroll
@@ -95,11 +123,20 @@ struct Lds {
   //       [63] barrier flag
   int32_t *misc;
   int32_t *rcnt;  // per-rule application counts of this workgroup
+  // statistics of this workgroup over every round it runs in the launch,
+  // flushed once at the end of the launch: STAT_* then gc rounds, full
+  // sweeps, peak extent
+  unsigned long long *lstat;
   Queue qd, qf, qr;  // dead, frontier, retire
 };
 
+#define LSTAT_GC CTL_NSTAT
+#define LSTAT_FULL (CTL_NSTAT + 1)
+#define LSTAT_PEAK (CTL_NSTAT + 2)
+#define LSTAT_N (CTL_NSTAT + 3)
+
 __device__ __forceinline__ void qpush(const Lds &L, const Queue &q, int32_t v, int64_t cap) {
-  int i = atomicAdd(&L.misc[q.slot], 1);
+  const int i = atomicAdd(&L.misc[q.slot], 1);
   if (i < q.cap_lds) {
     q.buf[i] = v;
   } else {  // LDS buffer full: append directly
@@ -179,9 +216,28 @@ __device__ __forceinline__ int xcd_remap(int wg, int G) {
   return (wg & 7) * (G >> 3) + (wg >> 3);
 }
 
+// phase timestamp (thread 0 of workgroup 0, when tracing is on)
+__device__ __forceinline__ void tmark(const RoundArgs &a, int r, int field) {
+  if (a.trace && blockIdx.x == 0 && threadIdx.x == 0 && r < a.trace_cap)
+    a.trace[(size_t)r * TRACE_FIELDS + field] = clock64();
+}
+
 struct Counters {
-  int active, ready, fired, nfset, alloc, freed, rcops, memo;
+  int active, ready, fired, nfset, alloc, freed, rcops, memo, mlp, keep, trace;
 };
+
+// Age bucket of the predictor's input: 0 for age 0, else
+// min(15, floor(log2 age) + 1).
+__device__ __forceinline__ int age_bucket(int age) {
+  return age <= 0 ? 0 : min(15, 32 - __clz(age));
+}
+
+// The predictor's keep decision for (symbol, argument normal-form bits, age
+// bucket), from the decision table held in LDS.
+__device__ __forceinline__ bool gate_keep(const Lds &L, int off, int sym, int bits, int bucket) {
+  const int i = ((sym * 32 + bits) << 4) | bucket;
+  return (L.tab[off + (i >> 5)] >> (i & 31)) & 1;
+}
 
 // visible normal form in round parity e (markers of the current parity are
 // not yet valid)
@@ -216,6 +272,24 @@ __device__ __forceinline__ void notify_parent(const RoundArgs &a, const Lds &L, 
   }
 }
 
+// Bit 0 of each byte of x, packed into bits 0-3 (the four products land on
+// distinct bit positions, so no carries mix them).
+__device__ __forceinline__ int pack4(unsigned x) {
+  return (int)((((x & 0x01010101u) * 0x01020408u) >> 24) & 0xFu);
+}
+
+// Plain mode: tell the parent of a node that just became a normal form to
+// test itself again (from the next round on: the bit of this round's parity
+// is honoured only by rounds of the other parity).  A 32-bit atomic OR on the
+// word that holds the parent's wake byte.
+__device__ __forceinline__ void wake_parent(const RoundArgs &a, const RoundCtx &R, int s) {
+  const int par = a.p.par[s];
+  if (par > 0 && par < a.p.N) {
+    unsigned *w = reinterpret_cast<unsigned *>(a.p.wake + (par & ~3));
+    atomicOr(w, (1u << R.e) << (8 * (par & 3)));
+  }
+}
+
 // Examine slot s (s <= 0: idle lane) and rewrite it if it is a redex whose
 // arguments are all normal forms.  memo: the slot's memo bits.  Must be
 // called by every thread of the workgroup (contains the allocation barrier);
@@ -230,11 +304,14 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
   const unsigned e = R.e;
   const int64_t N = p.N;
   const bool frontier = R.mode != 0;
+  const bool track = R.mode == 2 || a.trace_rate != 0;  // keep lastchg
   RoundCnt *cnt = R.cnt;
   bool have = s > 0;
-  int info = 0, ar = 0;
+  int info = 0, ar = 0, f = 0;
   ivec8 av = (ivec8)(0);
   bool ready = false;
+  int nfb = -1;  // >= 0: the slot was examined and is blocked; bit j set when
+                 // argument j is a visible normal form or j >= arity
   if (have) {
     if (!memo_checked) C.active++;
     bool blocked = false;
@@ -244,7 +321,7 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
       C.memo += blocked;
     }
     if (!blocked) {
-      const int f = p.hss[s];
+      f = p.hss[s];
       if ((unsigned)f >= (unsigned)a.n_sym) {
         cnt->err = -9;
       } else {
@@ -262,17 +339,57 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
         if (!ok) {
           cnt->err = -9;
         } else {
-          int first_blocked = 0;
+          int bits = 0;
 #pragma unroll
-          for (int j = A - 1; j >= 0; j--)
-            if (j < ar && !nf_visible(p.state[av[j]], e)) first_blocked = j + 1;
-          ready = first_blocked == 0;
-          if (!ready && first_blocked != memo)
-            p.state[s] = (uint8_t)(ST_ACTIVE | (first_blocked << ST_MEMO_SHIFT));
+          for (int j = 0; j < 5; j++)
+            if (j >= ar || (j < A && nf_visible(p.state[av[j]], e))) bits |= 1 << j;
+          ready = bits == 31;
+          if (!ready) {
+            if (a.use_memo) {
+              const int first_blocked = __builtin_ctz(~bits) + 1;
+              if (first_blocked != memo)
+                p.state[s] = (uint8_t)(ST_ACTIVE | (first_blocked << ST_MEMO_SHIFT));
+            } else {
+              nfb = bits;
+            }
+          }
         }
       }
     }
   }
+  if (nfb >= 0) {
+    // a blocked node without the memo shortcut: learned mode asks the
+    // predictor whether to examine it again next round; tracing samples it
+    const int bk = age_bucket(R.r - p.lastchg[s]);
+    if (R.mode == 2) {
+      C.mlp++;
+      if (gate_keep(L, a.gate_off, f, nfb, bk)) {
+        C.keep++;
+        qpush(L, L.qf, s, N);
+      }
+    } else if (a.trace_rate) {
+      const uint32_t h = mix32((uint32_t)s * 0x9E3779B1u ^ (uint32_t)R.r * 0x85EBCA77u);
+      // (appends stop once the buffer is full, so the counter cannot wrap)
+      if ((h & 0xffffu) < a.trace_rate && ld(a.trace_n) < a.trace_cap_rec) {
+        C.trace++;
+        const int idx = atomicAdd(a.trace_n, 1);
+        if (idx >= 0 && idx < a.trace_cap_rec) {
+          a.trace_rec[idx] = (unsigned long long)f | ((unsigned long long)ar << 16) |
+                             ((unsigned long long)nfb << 20) | ((unsigned long long)bk << 25);
+          p.tref[s] = ((long long)idx << 32) | (unsigned)R.r;
+        }
+      }
+    }
+  }
+  if (ready && a.trace_rate && R.r > 0) {
+    // label of the node's record from the previous round: it can fire or
+    // become a normal form now
+    const long long t = p.tref[s];
+    const long long idx = t >> 32;
+    if ((int)(t & 0xffffffff) == R.r - 1 && idx >= 0 && idx < a.trace_cap_rec)
+      a.trace_rec[idx] |= 1ull << 32;
+  }
+  tmark(a, R.r, 6);
   int prog = -1;
   bool nfset = false;
   ivec16 ps = (ivec16)(0);  // ps[k]: slot matched by pattern node k (0 = the redex)
@@ -320,7 +437,9 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
   const int hdr = prog >= 0 ? tab[prog] : 0;
   const int m = (hdr >> 4) & 15;
   C.alloc += m;
+  tmark(a, R.r, 7);
   const int2 base = wg_reserve2(L, m, &cnt->alloc, free_slot > 0 ? 1 : 0, &cnt->push);
+  tmark(a, R.r, 8);
   if (free_slot > 0) {
     if ((int64_t)fsQ + base.y < N)
       SQ[fsQ + base.y] = free_slot;
@@ -352,6 +471,7 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
     const int npos = (hdr >> 12) & 15, nneg = (hdr >> 16) & 15, rootpat = (hdr >> 20) & 15;
     // new nodes, children before parents
     int q = no;
+    int bornmask = 0;  // bit j: new node j was born a normal form
     for (int j = 0; j < m; j++) {
       const int h = tab[q];
       const int sym = h & 0xffff, rci = (h >> 16) & 0x3f, bnf = (h >> 22) & 1;
@@ -368,15 +488,33 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
       p.hss[slot] = sym;
       p.rc[slot] = rci;
       p.state[slot] = bnf ? (uint8_t)ST_NF : (uint8_t)(ST_ACTIVE | ST_PEND | (e << 2));
-      if (frontier) {
-        p.par[slot] = refr ? ns[refr - 1] : s;
-        if (!bnf) {
-          if (nready)
-            qpush(L, L.qf, slot, N);  // examined next round (retires its own marker)
-          else
-            qpush(L, L.qr, slot, N);
+      if (track) p.lastchg[slot] = R.r;
+      if (R.mode <= 1) p.par[slot] = refr ? ns[refr - 1] : s;
+      if (frontier && !bnf) {
+        bool keep = nready;
+        if (!keep && R.mode == 2) {
+          // its arguments: matched pattern nodes are normal forms (every
+          // node below an innermost redex is), new ones by their born_nf flag
+          int bits = 0;
+#pragma unroll
+          for (int o = 0; o < 5; o++) {
+            if (o >= ar2) {
+              bits |= 1 << o;
+            } else if (o < A) {
+              const int v = tab[q + 1 + o];
+              if (v >= 0 || ((bornmask >> (-1 - v)) & 1)) bits |= 1 << o;
+            }
+          }
+          C.mlp++;
+          keep = gate_keep(L, a.gate_off, sym, bits, 0);
+          C.keep += keep;
         }
+        if (keep)
+          qpush(L, L.qf, slot, N);  // examined next round (retires its own marker)
+        else
+          qpush(L, L.qr, slot, N);
       }
+      bornmask |= bnf << j;
       q += 1 + ar2;
     }
     // the redex root is overwritten in place
@@ -403,10 +541,10 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
       }
       p.hss[s] = sh;
       p.state[s] = pend_nf;
-      if (frontier) {
-        notify_parent(a, L, R, s);
-        qpush(L, L.qr, s, N);
-      }
+      if (track) p.lastchg[s] = R.r;
+      if (R.mode == 1) notify_parent(a, L, R, s);
+      if (R.mode == 0 && a.use_memo) wake_parent(a, R, s);
+      if (frontier) qpush(L, L.qr, s, N);
     } else {
       const int rar = tab[TAB_SYM + rsym] & 0xff;
 #pragma unroll
@@ -417,15 +555,33 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
         }
       }
       p.hss[s] = rsym;
+      if (track) p.lastchg[s] = R.r;
       if (root_nf) {
         p.state[s] = pend_nf;
-        if (frontier) {
-          notify_parent(a, L, R, s);
-          qpush(L, L.qr, s, N);
-        }
+        if (R.mode == 1) notify_parent(a, L, R, s);
+        if (R.mode == 0 && a.use_memo) wake_parent(a, R, s);
+        if (frontier) qpush(L, L.qr, s, N);
       } else {
         if (memo) p.state[s] = (uint8_t)ST_ACTIVE;  // the arguments changed: drop the memo
-        if (frontier && root_ready) qpush(L, L.qf, s, N);
+        if (frontier) {
+          bool keep = root_ready;
+          if (!keep && R.mode == 2) {
+            int bits = 0;
+#pragma unroll
+            for (int o = 0; o < 5; o++) {
+              if (o >= rar) {
+                bits |= 1 << o;
+              } else if (o < A) {
+                const int v = tab[ro + o];
+                if (v >= 0 || ((bornmask >> (-1 - v)) & 1)) bits |= 1 << o;
+              }
+            }
+            C.mlp++;
+            keep = gate_keep(L, a.gate_off, rsym, bits, 0);
+            C.keep += keep;
+          }
+          if (keep) qpush(L, L.qf, s, N);
+        }
       }
     }
     // reference counts: increments first, then decrements (a decrement that
@@ -442,16 +598,30 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
       if (old + d == 0) qpush(L, L.qd, slot, N);
     }
     C.rcops += npos + nneg;
-    atomicAdd(&L.rcnt[rid], 1);
   } else if (nfset) {
     C.nfset++;
     p.state[s] = pend_nf;
-    if (frontier) {
-      notify_parent(a, L, R, s);
-      qpush(L, L.qr, s, N);
+    if (track) p.lastchg[s] = R.r;
+    if (R.mode == 1) notify_parent(a, L, R, s);
+    if (R.mode == 0 && a.use_memo) wake_parent(a, R, s);
+    if (frontier) qpush(L, L.qr, s, N);
+  }
+  // per-rule counts: one LDS atomic per distinct rule among the wave's lanes
+  // (every lane of the wave runs this loop; its trip count is uniform)
+  {
+    const int rid = prog >= 0 ? tab[prog + 5] : -1;
+    unsigned long long pending = __ballot(rid >= 0);
+    while (pending) {
+      const int leader = __ffsll((long long)pending) - 1;
+      const int rl = __shfl(rid, leader, 64);
+      const unsigned long long same = __ballot(rid == rl);
+      if (lane() == leader) atomicAdd(&L.rcnt[rl], __popcll(same));
+      pending &= ~same;
     }
   }
+  tmark(a, R.r, 9);
   qflush(L, N);
+  tmark(a, R.r, 10);
 }
 
 // Collect dead node d: drop one reference to each argument, mark the slot
@@ -487,7 +657,10 @@ __device__ __forceinline__ int collect(const RoundArgs &a, const Lds &L, RoundCn
 // State of round r, derived from the counters of round r-1.
 struct RoundState {
   int r, n, fs0, fs1, nd, nfront, nret, nlist, ntiles, need, err;
-  bool stop, quiescent, full;
+  bool stop, quiescent, full, done;
+  bool stall;  // the previous round met live non-normal-form slots but made no
+               // progress: this round is a full sweep that tests every slot
+               // (plain mode: ignoring the wake bits)
 };
 
 // Thread 0 reads the previous round's counters and derives round r; the
@@ -498,13 +671,13 @@ struct RoundState {
 // need: number of workgroups the round uses -- 1 when its lists are small
 // (at most small_cap items), so that one workgroup can run consecutive small
 // rounds.
-__device__ RoundState round_state(const RoundArgs &a, int r) {
+__device__ __forceinline__ RoundState round_state(const RoundArgs &a, int r) {
   const Pool &p = a.p;
   Ctl *ctl = a.ctl;
   const int B = blockDim.x;
   RoundState rs;
   int n, fs0, fs1, nd = 0, nfront = 0, nret = 0, err = 0;
-  bool quiescent = false, stop = false;
+  bool quiescent = false, stop = false, stall = false;
   if (r == 0) {
     n = ld(&ctl->n[0]);
     fs0 = ld(&ctl->fs[0][0]);
@@ -514,6 +687,7 @@ __device__ RoundState round_state(const RoundArgs &a, int r) {
     const int c_alloc = ld(&ctl->cnt[p3].alloc), c_push = ld(&ctl->cnt[p3].push);
     const int c_dead = ld(&ctl->cnt[p3].dead), c_act = ld(&ctl->cnt[p3].active);
     const int c_err = ld(&ctl->cnt[p3].err), c_full = ld(&ctl->cnt[p3].full);
+    const int c_prog = ld(&ctl->cnt[p3].prog);
     nfront = ld(&ctl->cnt[p3].front);
     nret = ld(&ctl->cnt[p3].ret);
     const int pn = ld(&ctl->n[p3]), pf0 = ld(&ctl->fs[p3][0]), pf1 = ld(&ctl->fs[p3][1]);
@@ -533,6 +707,12 @@ __device__ RoundState round_state(const RoundArgs &a, int r) {
     // a full round that met no live non-normal-form slot: nothing can be
     // rewritten any more; remaining rounds only collect
     quiescent = c_full && c_act == 0;
+    // a round that met live non-normal-form slots but in which nothing fired
+    // or became a normal form: everything it examined waits on nodes it did
+    // not examine (a frontier that keeps only blocked nodes, or wake bits
+    // that missed a node with two parents); the next round is a full sweep
+    // that tests every slot
+    stall = c_act != 0 && c_prog == 0;
     stop = c_err != 0 || nn > p.N || (quiescent && c_dead == 0);
     err = c_err ? c_err : (nn > p.N ? -5 : 0);
   }
@@ -546,8 +726,10 @@ __device__ RoundState round_state(const RoundArgs &a, int r) {
   rs.nret = nret;
   rs.stop = stop;
   rs.quiescent = quiescent;
+  rs.stall = stall;
   rs.err = err;
-  rs.full = !quiescent && (a.mode == 0 || nfront == 0 || r == 0);
+  rs.done = false;
+  rs.full = !quiescent && (a.mode == 0 || nfront == 0 || r == 0 || stall);
   // in full rounds the sweep retires every marker, so the retire list is
   // skipped
   rs.nlist = nd + (rs.full ? 0 : nret + nfront);
@@ -558,34 +740,59 @@ __device__ RoundState round_state(const RoundArgs &a, int r) {
   return rs;
 }
 
-// round_state computed by thread 0 and shared with the workgroup via LDS.
-__device__ RoundState round_prepare(const RoundArgs &a, const Lds &L, int r) {
-  int32_t *bc = L.misc + 40;  // [40..46]
+// State of a round, shared with the workgroup via LDS.  from_pub: the
+// launch's first round, taken from the line the previous launch published
+// (plain loads: it was written before this launch began); otherwise thread 0
+// derives round r from the counters of round r-1.
+__device__ __forceinline__ RoundState round_prepare(const RoundArgs &a, const Lds &L, int r,
+                                                    bool from_pub) {
+  int32_t *bc = L.misc + 40;  // [40..49]
   if (threadIdx.x == 0) {
-    const RoundState t = round_state(a, r);
-    bc[0] = t.n;
-    bc[1] = t.fs0;
-    bc[2] = t.fs1;
-    bc[3] = t.nd;
-    bc[4] = t.nfront;
-    bc[5] = t.nret;
-    bc[6] = (t.stop ? 1 : 0) | (t.quiescent ? 2 : 0) | (t.err << 8);
+    if (from_pub) {
+      const int4 *pp = reinterpret_cast<const int4 *>(a.ctl->pub);
+      const int4 x = pp[0], y = pp[1], z = pp[2];
+      bc[0] = x.x;
+      bc[1] = x.y;
+      bc[2] = x.z;
+      bc[3] = x.w;
+      bc[4] = y.x;
+      bc[5] = y.y;
+      bc[6] = y.z;
+      bc[7] = y.w;
+      bc[8] = z.x;
+      bc[9] = z.y;
+    } else {
+      const RoundState t = round_state(a, r);
+      bc[0] = 0;
+      bc[1] = r;
+      bc[2] = t.need;
+      bc[3] = t.n;
+      bc[4] = t.fs0;
+      bc[5] = t.fs1;
+      bc[6] = t.nd;
+      bc[7] = t.nfront;
+      bc[8] = t.nret;
+      bc[9] = (t.stop ? 1 : 0) | (t.quiescent ? 2 : 0) | (t.stall ? 4 : 0) | (t.err << 8);
+    }
   }
   __syncthreads();
   RoundState rs;
   const int B = blockDim.x;
-  rs.r = r;
-  rs.n = bc[0];
-  rs.fs0 = bc[1];
-  rs.fs1 = bc[2];
-  rs.nd = bc[3];
-  rs.nfront = bc[4];
-  rs.nret = bc[5];
-  rs.stop = bc[6] & 1;
-  rs.quiescent = bc[6] & 2;
-  rs.err = bc[6] >> 8;
+  rs.done = bc[0] != 0;
+  rs.r = bc[1];
+  rs.n = bc[3];
+  rs.fs0 = bc[4];
+  rs.fs1 = bc[5];
+  rs.nd = bc[6];
+  rs.nfront = bc[7];
+  rs.nret = bc[8];
+  rs.stop = bc[9] & 1;
+  rs.quiescent = bc[9] & 2;
+  rs.stall = bc[9] & 4;
+  rs.err = bc[9] >> 8;
   __syncthreads();
-  rs.full = !rs.quiescent && (a.mode == 0 || rs.nfront == 0 || r == 0);
+  tmark(a, rs.r, 0);
+  rs.full = !rs.quiescent && (a.mode == 0 || rs.nfront == 0 || rs.r == 0 || rs.stall);
   rs.nlist = rs.nd + (rs.full ? 0 : rs.nret + rs.nfront);
   rs.ntiles = rs.full ? (rs.n + B * a.npt - 1) / (B * a.npt) : 0;
   rs.need = max((rs.nlist + B - 1) / B, rs.ntiles);
@@ -594,10 +801,22 @@ __device__ RoundState round_prepare(const RoundArgs &a, const Lds &L, int r) {
   return rs;
 }
 
+// Publish round nx for the next launch (one thread).
+__device__ __forceinline__ void publish(Ctl *ctl, const RoundState &nx) {
+  const int v[10] = {0,         nx.r,      nx.need,   nx.n,      nx.fs0,
+                     nx.fs1,    nx.nd,     nx.nfront, nx.nret,
+                     (nx.stop ? 1 : 0) | (nx.quiescent ? 2 : 0) | (nx.stall ? 4 : 0) |
+                         (nx.err << 8)};
+#pragma unroll
+  for (int i = 0; i < 10; i++)
+    __hip_atomic_store(&ctl->pub[i], v[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Record the end of the run (thread 0 of workgroup 0).
 __device__ __forceinline__ void round_stop(const RoundArgs &a, const RoundState &rs) {
   Ctl *ctl = a.ctl;
   ctl->done = 1;
+  ctl->pub[0] = 1;
   ctl->done_round = rs.r;
   ctl->err = rs.err;
   ctl->n_final = rs.n;
@@ -607,7 +826,7 @@ __device__ __forceinline__ void round_stop(const RoundArgs &a, const RoundState 
 // share of the lists and of the sweep.  Called only by workgroups below
 // rs.need; tables must be in LDS.
 template <int A>
-__device__ void round_execute(const RoundArgs &a, Lds &L, const RoundState &rs) {
+__device__ __forceinline__ void round_execute(const RoundArgs &a, Lds &L, const RoundState &rs) {
   const Pool &p = a.p;
   Ctl *ctl = a.ctl;
   const int B = blockDim.x, tid = threadIdx.x, wg = blockIdx.x;
@@ -616,23 +835,25 @@ __device__ void round_execute(const RoundArgs &a, Lds &L, const RoundState &rs) 
   const bool full = rs.full, quiescent = rs.quiescent;
   const int nlist = rs.nlist, ntiles = rs.ntiles, need = rs.need;
   const int G = gridDim.x;
+  tmark(a, r, 1);
   if (wg == 0 && tid == 0) {
     ctl->n[r3] = n;
     ctl->fs[r3][0] = fs0;
     ctl->fs[r3][1] = fs1;
     RoundCnt *nx = &ctl->cnt[(r + 1) % 3];
     nx->alloc = nx->push = nx->dead = nx->active = nx->err = nx->front = nx->ret = nx->full = 0;
+    nx->prog = 0;
     ctl->cnt[r3].full = (full || quiescent) ? 1 : 0;
-    if (n > ctl->peak_n) ctl->peak_n = n;
-    if (nd > 0) ctl->gc_rounds++;
-    if (full) ctl->full_sweeps++;
-    ctl->stat[STAT_VISITS][0] += (unsigned long long)(full ? n : nfront);
+    if ((unsigned long long)n > L.lstat[LSTAT_PEAK]) L.lstat[LSTAT_PEAK] = n;
+    if (nd > 0) L.lstat[LSTAT_GC]++;
+    if (full) L.lstat[LSTAT_FULL]++;
+    L.lstat[STAT_VISITS] += (unsigned long long)(full ? n : nfront);
   }
   // the first `need` workgroups run the round; list items and tiles are
   // strided over exactly those
   const int Ga = min(G, need);
   RoundCnt *cnt = &ctl->cnt[r3];
-  Counters C = {0, 0, 0, 0, 0, 0, 0, 0};
+  Counters C = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   RoundCtx R;
   R.r = r;
   R.n = n;
@@ -655,6 +876,7 @@ __device__ void round_execute(const RoundArgs &a, Lds &L, const RoundState &rs) 
   const int32_t *RT = ((r - 1) & 1) ? p.ret1 : p.ret0;
   const unsigned ep = (unsigned)((r - 1) & 1);
 
+  tmark(a, r, 2);
   // ---- 1. list items: collection, marker retirement, frontier slots
   {
     const int nr_here = full ? 0 : nret;
@@ -676,7 +898,7 @@ __device__ void round_execute(const RoundArgs &a, Lds &L, const RoundState &rs) 
           }
           if ((st & ST_ACTIVE) && !(st & ST_PEND)) {
             s = x;
-            memo = (int)((st & ST_MEMO_MASK) >> ST_MEMO_SHIFT);
+            memo = a.use_memo ? (int)((st & ST_MEMO_MASK) >> ST_MEMO_SHIFT) : 0;
           }
         }
       }
@@ -684,11 +906,13 @@ __device__ void round_execute(const RoundArgs &a, Lds &L, const RoundState &rs) 
     }
   }
 
+  tmark(a, r, 3);
   // ---- 2./3. full sweep of all slots below n, rewrite of the ready ones
   if (full) {
     const int npt = a.npt;
     const int TILE = B * npt;
     const unsigned e = R.e;
+    const bool wake_sweep = a.mode == 0 && a.use_memo && !rs.stall;
     for (int t = xcd_remap(wg, Ga); t < ntiles; t += Ga) {
       const int base = t * TILE + tid * npt;
       // state bytes of this thread's slots, kept in four registers
@@ -708,9 +932,29 @@ __device__ void round_execute(const RoundArgs &a, Lds &L, const RoundState &rs) 
       } else {
         for (int j = 0; j < npt; j++) sw[0] |= (int)p.state[base + j] << (8 * j);
       }
-      // classify the thread's slots; for live slots with a memo, read the
-      // recorded argument of all of them first, then all their states, so
-      // the dependent loads of the 16 slots overlap
+      // plain mode: the wake bits of the same slots, for the parity of the
+      // previous rounds, packed into a 16-bit mask (a sleeping slot -- one
+      // with a memo -- is tested again only once an argument has become a
+      // normal form in an earlier round)
+      int wmask = 0;
+      if (wake_sweep) {
+        const unsigned sh = 1u - e;
+        if (npt == 16) {
+          const uint4 v = *reinterpret_cast<const uint4 *>(p.wake + base);
+          wmask = pack4(v.x >> sh) | pack4(v.y >> sh) << 4 | pack4(v.z >> sh) << 8 |
+                  pack4(v.w >> sh) << 12;
+        } else if (npt == 8) {
+          const uint2 v = *reinterpret_cast<const uint2 *>(p.wake + base);
+          wmask = pack4(v.x >> sh) | pack4(v.y >> sh) << 4;
+        } else if (npt == 4) {
+          wmask = pack4(*reinterpret_cast<const uint32_t *>(p.wake + base) >> sh);
+        } else {
+          for (int j = 0; j < npt; j++) wmask |= (int)((p.wake[base + j] >> sh) & 1u) << j;
+        }
+      }
+      // classify the thread's slots; otherwise, for live slots with a memo,
+      // read the recorded argument of all of them first, then all their
+      // states, so the dependent loads of the 16 slots overlap
       ivec16 cidx = (ivec16)(0);   // memo argument slot (0: none)
       int pending = 0;             // bit j: slot j is live and not in normal form
 #pragma unroll
@@ -727,8 +971,8 @@ __device__ void round_execute(const RoundArgs &a, Lds &L, const RoundState &rs) 
             if (st == ST_NF) continue;
           }
           pending |= 1 << j;
-          const int memo = (int)((st & ST_MEMO_MASK) >> ST_MEMO_SHIFT);
-          if (memo) {
+          const int memo = a.use_memo ? (int)((st & ST_MEMO_MASK) >> ST_MEMO_SHIFT) : 0;
+          if (memo && !wake_sweep) {
             const int c = p.args[(int64_t)slot * A + (memo - 1)];
             cidx[j] = ((unsigned)c < (unsigned)p.N) ? c : 0;
           }
@@ -737,19 +981,29 @@ __device__ void round_execute(const RoundArgs &a, Lds &L, const RoundState &rs) 
       int cst[16];
 #pragma unroll
       for (int j = 0; j < 16; j++) cst[j] = (pending >> j & 1) && cidx[j] ? p.state[cidx[j]] : 0;
+      // compact the slots to examine into the LDS work list (the loop is
+      // uniform: every lane takes part in each wave-wide reservation)
 #pragma unroll
       for (int j = 0; j < 16; j++) {
-        if (!(pending >> j & 1)) continue;
-        C.active++;
-        const int slot = base + j;
+        if (j >= npt) break;
+        const bool live = pending >> j & 1;
         const unsigned byte = ((unsigned)sw[j >> 2] >> ((j & 3) * 8)) & 0xffu;
-        const int memo = (byte & ST_PEND) ? 0 : (int)((byte & ST_MEMO_MASK) >> ST_MEMO_SHIFT);
-        if (memo && cidx[j] && !nf_visible((unsigned)cst[j], e)) {
-          C.memo++;  // still blocked by the same argument
-          continue;
+        const int memo = (!live || (byte & ST_PEND) || !a.use_memo)
+                             ? 0
+                             : (int)((byte & ST_MEMO_MASK) >> ST_MEMO_SHIFT);
+        const bool still = wake_sweep ? (memo && !((wmask >> j) & 1))
+                                      : (memo && cidx[j] && !nf_visible((unsigned)cst[j], e));
+        if (memo && !still && wake_sweep) {
+          // honour (clear) the wake bit of the previous rounds' parity; a bit
+          // set in this round stays for the next one
+          const int slot = base + j;
+          atomicAnd(reinterpret_cast<unsigned *>(p.wake + (slot & ~3)),
+                    ~((1u << (1u - e)) << (8 * (slot & 3))));
         }
-        const int w = atomicAdd(&L.misc[0], 1);
-        L.work[w] = slot | (memo << 29);
+        C.active += live;
+        C.memo += still;  // still blocked by the same argument
+        const int w = wave_reserve(live && !still, &L.misc[0]);
+        if (w >= 0) L.work[w] = (base + j) | (memo << 29);
       }
       __syncthreads();
       const int W = L.misc[0];
@@ -765,39 +1019,65 @@ __device__ void round_execute(const RoundArgs &a, Lds &L, const RoundState &rs) 
     }
   }
 
-  // ---- per-workgroup statistics
-  atomicAdd(&L.misc[32], C.active);
-  atomicAdd(&L.misc[33], C.ready);
-  atomicAdd(&L.misc[34], C.fired);
-  atomicAdd(&L.misc[35], C.nfset);
-  atomicAdd(&L.misc[36], C.alloc);
-  atomicAdd(&L.misc[37], C.freed);
-  atomicAdd(&L.misc[38], C.rcops);
-  atomicAdd(&L.misc[39], C.memo);
+  tmark(a, r, 4);
+  // ---- per-workgroup statistics: wave sums, added by one lane per wave to
+  // the workgroup's LDS totals; only the liveness flag of the round goes to
+  // global memory
+  {
+    const int sa = wave_sum(C.active), sr = wave_sum(C.ready), sf = wave_sum(C.fired);
+    const int sn = wave_sum(C.nfset), sl = wave_sum(C.alloc), sd = wave_sum(C.freed);
+    const int so = wave_sum(C.rcops), sm = wave_sum(C.memo);
+    const int sp = wave_sum(C.mlp), sk = wave_sum(C.keep), st = wave_sum(C.trace);
+    if (lane() == 0) {
+      if (sa) {
+        L.misc[32] = 1;
+        atomicAdd(&L.lstat[STAT_ACTIVE], (unsigned long long)sa);
+      }
+      if (sf || sn) L.misc[33] = 1;
+      if (sr) atomicAdd(&L.lstat[STAT_READY], (unsigned long long)sr);
+      if (sf) atomicAdd(&L.lstat[STAT_FIRED], (unsigned long long)sf);
+      if (sn) atomicAdd(&L.lstat[STAT_NFSET], (unsigned long long)sn);
+      if (sl) atomicAdd(&L.lstat[STAT_ALLOC], (unsigned long long)sl);
+      if (sd) atomicAdd(&L.lstat[STAT_FREED], (unsigned long long)sd);
+      if (so) atomicAdd(&L.lstat[STAT_RCOPS], (unsigned long long)so);
+      if (sm) atomicAdd(&L.lstat[STAT_MEMO], (unsigned long long)sm);
+      if (sp) atomicAdd(&L.lstat[STAT_MLP], (unsigned long long)sp);
+      if (sk) atomicAdd(&L.lstat[STAT_KEEP], (unsigned long long)sk);
+      if (st) atomicAdd(&L.lstat[STAT_TRACE], (unsigned long long)st);
+    }
+  }
+  __syncthreads();
+  if (tid == 0 && L.misc[32]) {
+    cnt->active = 1;
+    L.misc[32] = 0;
+  }
+  if (tid == 0 && L.misc[33]) {
+    cnt->prog = 1;
+    L.misc[33] = 0;
+  }
+  __syncthreads();
+  tmark(a, r, 5);
+}
+
+// Add this workgroup's statistics of the launch to the control block (once,
+// at the end of the launch).
+__device__ __forceinline__ void flush_stats(const RoundArgs &a, const Lds &L) {
+  Ctl *ctl = a.ctl;
+  const int wg = blockIdx.x, tid = threadIdx.x;
   __syncthreads();
   if (tid == 0) {
     const int sp = wg & (CTL_SPREAD - 1);
-    if (L.misc[32]) {
-      cnt->active = 1;
-      atomicAdd(&ctl->stat[STAT_ACTIVE][sp], (unsigned long long)L.misc[32]);
-    }
-    if (L.misc[33]) atomicAdd(&ctl->stat[STAT_READY][sp], (unsigned long long)L.misc[33]);
-    if (L.misc[34]) atomicAdd(&ctl->stat[STAT_FIRED][sp], (unsigned long long)L.misc[34]);
-    if (L.misc[35]) atomicAdd(&ctl->stat[STAT_NFSET][sp], (unsigned long long)L.misc[35]);
-    if (L.misc[36]) atomicAdd(&ctl->stat[STAT_ALLOC][sp], (unsigned long long)L.misc[36]);
-    if (L.misc[37]) atomicAdd(&ctl->stat[STAT_FREED][sp], (unsigned long long)L.misc[37]);
-    if (L.misc[38]) atomicAdd(&ctl->stat[STAT_RCOPS][sp], (unsigned long long)L.misc[38]);
-    if (L.misc[39]) atomicAdd(&ctl->stat[STAT_MEMO][sp], (unsigned long long)L.misc[39]);
-    for (int i = 32; i < 40; i++) L.misc[i] = 0;
+    for (int k = 0; k < CTL_NSTAT; k++)
+      if (L.lstat[k]) atomicAdd(&ctl->stat[k][sp], L.lstat[k]);
+    if (L.lstat[LSTAT_GC]) atomicAdd((unsigned *)&ctl->gc_rounds, (unsigned)L.lstat[LSTAT_GC]);
+    if (L.lstat[LSTAT_FULL])
+      atomicAdd((unsigned *)&ctl->full_sweeps, (unsigned)L.lstat[LSTAT_FULL]);
+    if (L.lstat[LSTAT_PEAK]) atomicMax(&ctl->peak_n, (int)L.lstat[LSTAT_PEAK]);
   }
-  for (int i = tid; i < a.n_rules; i += B) {
+  for (int i = tid; i < a.n_rules; i += blockDim.x) {
     const int c = L.rcnt[i];
-    if (c) {
-      atomicAdd(&ctl->rule_apps[i][wg & 3], (unsigned long long)c);
-      L.rcnt[i] = 0;
-    }
+    if (c) atomicAdd(&ctl->rule_apps[i][wg & 3], (unsigned long long)c);
   }
-  __syncthreads();
 }
 
 __device__ __forceinline__ Lds setup_lds(const RoundArgs &a, int32_t *smem, bool load_tab) {
@@ -815,10 +1095,11 @@ __device__ __forceinline__ Lds setup_lds(const RoundArgs &a, int32_t *smem, bool
   L.qf.slot = 2;
   L.qr.slot = 3;
   L.misc = q + 3 * qc;
-  L.rcnt = L.misc + 64;
+  L.lstat = reinterpret_cast<unsigned long long *>(L.misc + 64);
+  L.rcnt = L.misc + 64 + 2 * 16;
   if (load_tab)
     for (int i = threadIdx.x; i < a.tab_words; i += B) L.tab[i] = a.tab[i];
-  for (int i = threadIdx.x; i < 64; i += B) L.misc[i] = 0;
+  for (int i = threadIdx.x; i < 64 + 2 * 16; i += B) L.misc[i] = 0;
   for (int i = threadIdx.x; i < a.n_rules; i += B) L.rcnt[i] = 0;
   __syncthreads();
   return L;
@@ -847,22 +1128,18 @@ template <int A>
 __global__ void __launch_bounds__(1024) k_round(RoundArgs a) {
   extern __shared__ int32_t smem[];
   Ctl *ctl = a.ctl;
-  if (ld(&ctl->done)) return;
   Lds L = setup_lds(a, smem, false);  // tables are loaded only by workgroups with work
   const int wg = blockIdx.x, tid = threadIdx.x;
-  // the number of workgroups this launch's first round uses was published
-  // by the previous launch; the others leave without reading any round
+  // the first round of this launch, as published by the previous launch;
+  // workgroups beyond the number it uses leave without reading any round
   // counter (workgroup 0 may already be running later rounds alone)
-  const int need0 = bcast(L, tid == 0 ? ld(&ctl->next_need) : 0);
-  int r = 0;
-  if (wg < need0) {
-    r = bcast(L, tid == 0 ? ld(&ctl->r_cur) : 0);
-    RoundState rs = round_prepare(a, L, r);
+  RoundState rs = round_prepare(a, L, 0, true);
+  if (rs.done) return;
+  if (wg < rs.need) {
     if (rs.stop) {
       if (wg == 0 && tid == 0) round_stop(a, rs);
       return;
     }
-    if (rs.need != need0 && tid == 0) ctl->cnt[r % 3].err = -9;  // inconsistent counters
     const bool alone = rs.need == 1;
     load_tables(a, L);
     // one call site: the first round, then (workgroup 0 alone) the
@@ -870,13 +1147,15 @@ __global__ void __launch_bounds__(1024) k_round(RoundArgs a) {
     for (int k = 0;; k++) {
       round_execute<A>(a, L, rs);
       if (!alone || k + 1 >= a.cont_rounds) break;
-      rs = round_prepare(a, L, rs.r + 1);
+      rs = round_prepare(a, L, rs.r + 1, false);
       if (rs.stop) {
+        flush_stats(a, L);
         if (tid == 0) round_stop(a, rs);
         return;
       }
       if (rs.need != 1) break;
     }
+    flush_stats(a, L);
     if (alone && tid == 0)
       __hip_atomic_store(&ctl->r_reached, rs.stop || rs.need == 1 ? rs.r + 1 : rs.r,
                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -890,6 +1169,7 @@ __global__ void __launch_bounds__(1024) k_round(RoundArgs a) {
       __threadfence();
       const int rr = max(ld(&ctl->r_cur) + 1, ld(&ctl->r_reached));
       const RoundState nx = round_state(a, rr);
+      publish(ctl, nx);
       __hip_atomic_store(&ctl->next_need, nx.need, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_store(&ctl->ticket, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_store(&ctl->r_cur, rr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -939,19 +1219,25 @@ __global__ void __launch_bounds__(1024) k_persistent(RoundArgs a) {
   const int r0 = bcast(L, threadIdx.x == 0 ? ld(&ctl->r_cur) : 0);
   int r = r0;
   for (int k = 0; k < a.nrounds; k++, r++) {
-    RoundState rs = round_prepare(a, L, r);
+    RoundState rs = round_prepare(a, L, r, false);
     if (rs.stop) {
+      flush_stats(a, L);
       if (blockIdx.x == 0 && threadIdx.x == 0) round_stop(a, rs);
       return;
     }
     if ((int)blockIdx.x < rs.need) round_execute<A>(a, L, rs);
-    if (!grid_barrier(a.bar, G * (unsigned long long)(k + 1), &ctl->abort, &L.misc[63])) return;
+    if (!grid_barrier(a.bar, G * (unsigned long long)(k + 1), &ctl->abort, &L.misc[63])) {
+      flush_stats(a, L);
+      return;
+    }
   }
+  flush_stats(a, L);
   // every workgroup read r_cur before the first barrier
   if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const RoundState nx = round_state(a, r);
+    publish(ctl, nx);
     __hip_atomic_store(&ctl->r_cur, r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(&ctl->next_need, round_state(a, r).need, __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&ctl->next_need, nx.need, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -959,7 +1245,7 @@ __global__ void __launch_bounds__(1024) k_persistent(RoundArgs a) {
 
 size_t trs_round_lds_bytes(int block, int npt, int tab_words, int n_rules) {
   size_t words = (size_t)((tab_words + 3) & ~3) + (size_t)block * npt +
-                 (size_t)3 * QBUF_PER_THREAD * block + 64 + (size_t)n_rules;
+                 (size_t)3 * QBUF_PER_THREAD * block + 64 + 2 * 16 + (size_t)n_rules;
   return words * sizeof(int32_t);
 }
 

@@ -64,6 +64,11 @@
 // Delta word: pattern node | (delta & 0xff)<<8 (signed 8-bit delta).
 #define TAB_SYM 4
 #define TAB_MAX_WORDS 4096
+// Learned mode appends the predictor's decision table to the rule tables
+// (both are copied into LDS together): bit ((sym*32 + c)*16 + bucket), c the
+// 5-bit mask of arguments in normal form (set for positions >= arity) and
+// bucket the age bucket, is 1 when the node is kept.  n_sym*16 words.
+#define TAB_GATE_MAX_WORDS 4096
 
 static inline int32_t tab_sym_word(int32_t arity, int32_t nrules, int32_t first) {
   return arity | (nrules << 8) | (first << 16);
@@ -71,7 +76,7 @@ static inline int32_t tab_sym_word(int32_t arity, int32_t nrules, int32_t first)
 
 // ---------------------------------------------------------------- control
 #define CTL_SPREAD 64    // statistics counters are spread over this many words
-#define CTL_NSTAT 10
+#define CTL_NSTAT 12
 enum {
   STAT_ACTIVE = 0,  // live non-normal-form slots visited
   STAT_READY,       // of those, all arguments in normal form
@@ -83,6 +88,8 @@ enum {
   STAT_MLP,         // predictor evaluations
   STAT_RCOPS,       // reference-count atomics (rewrite and collection)
   STAT_MEMO,        // active slots found still blocked by their memo argument
+  STAT_KEEP,        // predictor decisions that kept the node
+  STAT_TRACE,       // trace records logged (including ones past the cap)
 };
 
 struct RoundCnt {
@@ -94,6 +101,7 @@ struct RoundCnt {
   int32_t front;   // appends to the next round's frontier
   int32_t ret;     // appends to the retire list
   int32_t full;    // the round examined every slot (full sweep)
+  int32_t prog;    // a node fired or became a normal form in the round
 };
 
 struct Ctl {
@@ -114,6 +122,10 @@ struct Ctl {
   int32_t r_reached;   // round after the last one workgroup 0 ran alone
   int32_t pad2[3];
   RoundCnt cnt[3];     // counters accumulated during round r (index r % 3)
+  // state of the next launch's first round, published by the last workgroup
+  // of a launch (the host writes it for round 0): done, r, need, n, fs0, fs1,
+  // dead, frontier, retire, flags (stop | quiescent<<1 | stall<<2 | err<<8)
+  alignas(64) int32_t pub[16];
   unsigned long long stat[CTL_NSTAT][CTL_SPREAD];
   unsigned long long rule_apps[256][4];
 };
@@ -131,5 +143,12 @@ struct Pool {
   int32_t *front0, *front1; // frontier of the next round (round r appends to r&1)
   int32_t *ret0, *ret1;     // markers set in round r to retire in round r+1
   int32_t *qstamp;          // last notification stamp (deduplicates appends)
+  // plain mode: wake bits (bit p: an argument of the node became a normal
+  // form in a round of parity p since the node was last examined)
+  uint8_t *wake;
+  // learned mode and tracing
+  int32_t *lastchg;         // round in which the node was created or last changed
+  int64_t *tref;            // tracing: record index << 32 | round of the
+                            // node's latest trace record
   int64_t N;
 };

@@ -59,23 +59,33 @@ __global__ void k_atomics(uint32_t *a, size_t n, int k) {
   for (int j = 0; j < k; j++) atomicAdd(&a[mix32(t * 977u + j * 7919u) % n], 1u);
 }
 
-// one thread follows a chain of n dependent loads through a[]: each value
-// is the next index
-__global__ void k_chase(const uint32_t *a, int steps, uint32_t start, uint32_t *out) {
-  uint32_t i = start;
+// one wave follows 64 independent chains of dependent loads through a[]
+// (each value is the next index): per-lane addresses keep the loads on the
+// vector memory path; the time per step is one load latency
+__global__ void k_chase(const uint32_t *a, int steps, uint32_t start, uint32_t n,
+                        uint32_t *out) {
+  uint32_t i = (start + threadIdx.x * 4099u) % n;  // on the cycle of length n
   for (int j = 0; j < steps; j++) i = a[i];
-  out[0] = i;
+  out[threadIdx.x] = i;
 }
 
-// one thread performs n dependent returning atomics: the address of each
-// depends on the value returned by the previous one
+// one wave performs 64 independent chains of dependent returning atomics:
+// the address of each depends on the value returned by the previous one
 __global__ void k_atomic_chain(uint32_t *a, size_t n, int steps, uint32_t *out) {
-  uint32_t i = 0;
+  uint32_t i = (threadIdx.x * 977u) % n;
   for (int j = 0; j < steps; j++) {
-    const uint32_t v = atomicAdd(&a[i], 0u);
-    i = mix32(v + j) % n;
+    const uint32_t v = atomicAdd(&a[i], 1u);
+    i = mix32(v + j + threadIdx.x) % n;
   }
-  out[0] = i;
+  out[threadIdx.x] = i;
+}
+
+// plain copy of n uint4 (calibrates the memory counters: n*16 bytes read
+// and n*16 bytes written)
+__global__ void k_copy(const uint4 *a, uint4 *b, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    b[i] = a[i];
 }
 
 }  // namespace
@@ -150,7 +160,7 @@ extern "C" trs_status trs_membench(int32_t device, trs_membench_result *out) {
       }
       (void)hipMemcpy(a, h, nchase * 4, hipMemcpyHostToDevice);
       const int steps = 20000;
-      ms = timed([&] { hipLaunchKernelGGL(k_chase, dim3(1), dim3(1), 0, s, (const uint32_t *)a, steps, 1u, sink); }, 2);
+      ms = timed([&] { hipLaunchKernelGGL(k_chase, dim3(1), dim3(64), 0, s, (const uint32_t *)a, steps, 1u, (uint32_t)nchase, sink); }, 2);
       out->load_latency_far_ns = ms * 1e6 / steps;
       const size_t nsm = 64 << 10;  // 256 KiB
       for (size_t i = 0; i < nsm; i++) h[i] = (uint32_t)i;
@@ -164,16 +174,24 @@ extern "C" trs_status trs_membench(int32_t device, trs_membench_result *out) {
         h[j] = t;
       }
       (void)hipMemcpy(a, h, nsm * 4, hipMemcpyHostToDevice);
-      ms = timed([&] { hipLaunchKernelGGL(k_chase, dim3(1), dim3(1), 0, s, (const uint32_t *)a, steps, 1u, sink); }, 2);
+      ms = timed([&] { hipLaunchKernelGGL(k_chase, dim3(1), dim3(64), 0, s, (const uint32_t *)a, steps, 1u, (uint32_t)nsm, sink); }, 2);
       out->load_latency_near_ns = ms * 1e6 / steps;
       free(h);
     }
     const int asteps = 5000;
-    ms = timed([&] { hipLaunchKernelGGL(k_atomic_chain, dim3(1), dim3(1), 0, s, a, (size_t)64 << 10, asteps, sink); }, 2);
+    ms = timed([&] { hipLaunchKernelGGL(k_atomic_chain, dim3(1), dim3(64), 0, s, a, (size_t)64 << 10, asteps, sink); }, 2);
     out->atomic_latency_ns = ms * 1e6 / asteps;
   }
+  // copy of 256 MiB into a second buffer (the upper half of the 2 GiB block)
+  {
+    const size_t cb = (size_t)256 << 20;
+    uint4 *src = (uint4 *)a, *dst = (uint4 *)((char *)a + ((size_t)1 << 30));
+    ms = timed([&] { hipLaunchKernelGGL(k_copy, dim3(G), dim3(B), 0, s, (const uint4 *)src, dst, cb / 16); }, 5);
+    out->copy_gbps = 2.0 * cb / (ms * 1e-3) / 1e9;
+    out->copy_bytes = (int64_t)cb;
+  }
   // launch: an empty chain of small kernels
-  ms = timed([&] { hipLaunchKernelGGL(k_chase, dim3(1), dim3(1), 0, s, (const uint32_t *)a, 0, 0u, sink); }, 200);
+  ms = timed([&] { hipLaunchKernelGGL(k_chase, dim3(1), dim3(1), 0, s, (const uint32_t *)a, 0, 0u, 1u, sink); }, 200);
   out->empty_kernel_us = ms * 1e3;
   (void)hipStreamSynchronize(s);
   (void)hipFree(a);

@@ -37,14 +37,15 @@ class trs_opts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("block", ctypes.c_int32),
                 ("nodes_per_thread", ctypes.c_int32), ("rounds_per_poll", ctypes.c_int32),
                 ("max_rounds", ctypes.c_int64), ("threshold", ctypes.c_float),
-                ("persistent", ctypes.c_int32), ("trace", ctypes.c_int32)]
+                ("persistent", ctypes.c_int32), ("trace", ctypes.c_int32),
+                ("trace_cap", ctypes.c_int64)]
 
 
 class trs_stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in (
         "rounds", "rule_apps", "node_visits", "active_visits", "allocs", "frees",
         "peak_slots", "gc_rounds", "mlp_evals", "full_sweeps", "launches", "ready_visits",
-        "nf_set", "rc_atomics", "memo_blocked")] + [
+        "nf_set", "rc_atomics", "memo_blocked", "mlp_kept", "trace_records")] + [
         ("device_ms", ctypes.c_double)]
 
     def as_dict(self):
@@ -55,16 +56,51 @@ class trs_membench_result(ctypes.Structure):
     _fields_ = [(n, ctypes.c_double) for n in (
         "stream_read_gbps", "gather4_hbm_gops", "gather4_llc_gops", "gather1_llc_gops",
         "atomic_random_gops", "load_latency_far_ns", "load_latency_near_ns",
-        "atomic_latency_ns", "empty_kernel_us", "clock_mhz")] + [
+        "atomic_latency_ns", "empty_kernel_us")] + [
+        ("copy_gbps", ctypes.c_double), ("copy_bytes", ctypes.c_int64),
+        ("clock_mhz", ctypes.c_double),
         ("l2_bytes", ctypes.c_int64), ("cu_count", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_ if n != "pad"}
 
 
+class trs_train_opts(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_float),
+                ("val_frac", ctypes.c_float)]
+
+
+class trs_train_result(ctypes.Structure):
+    _fields_ = [("epochs_run", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("train_loss", ctypes.c_float * 64), ("val_loss", ctypes.c_float * 64),
+                ("device_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        k = self.epochs_run
+        return {"epochs_run": k, "train_loss": list(self.train_loss[:k]),
+                "val_loss": list(self.val_loss[:k]), "device_ms": self.device_ms}
+
+
+class trs_tune_result(ctypes.Structure):
+    _fields_ = [("trials", ctypes.c_int32), ("best_block", ctypes.c_int32),
+                ("best_npt", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("best_ms", ctypes.c_double), ("block", ctypes.c_int32 * 8),
+                ("npt", ctypes.c_int32 * 8), ("ms", ctypes.c_double * 8)]
+
+    def as_dict(self):
+        k = self.trials
+        return {"trials": k, "best_block": self.best_block, "best_npt": self.best_npt,
+                "best_ms": self.best_ms,
+                "table": [(self.block[i], self.npt[i], self.ms[i]) for i in range(k)]}
+
+
+TRS_MLP_EMB, TRS_MLP_DIN, TRS_MLP_H, TRS_MLP_MAX_SYM = 16, 24, 32, 256
+
 EXPORTS = ["trs_create", "trs_destroy", "trs_load_rules", "trs_load_terms", "trs_normalize",
            "trs_read_nf", "trs_rule_counts", "trs_default_opts", "trs_device_bytes",
-           "trs_membench", "trs_status_str", "trs_last_error"]
+           "trs_membench", "trs_status_str", "trs_last_error", "trs_mlp_param_count",
+           "trs_mlp_eval", "trs_mlp_train", "trs_mlp_table", "trs_set_predictor",
+           "trs_read_trace", "trs_autotune"]
 
 
 def _load_lib():
@@ -100,6 +136,25 @@ def _load_lib():
     lib.trs_status_str.restype = ctypes.c_char_p
     lib.trs_last_error.argtypes = [vp]
     lib.trs_last_error.restype = ctypes.c_char_p
+    u16p, u32p, u64p, f32p = (P(ctypes.c_uint16), P(ctypes.c_uint32), P(ctypes.c_uint64),
+                              P(ctypes.c_float))
+    lib.trs_mlp_param_count.argtypes = [ctypes.c_int32]
+    lib.trs_mlp_param_count.restype = ctypes.c_int64
+    lib.trs_mlp_eval.argtypes = [ctypes.c_int32, ctypes.c_int32, u16p, ctypes.c_int64, u64p,
+                                 P(ctypes.c_double), f32p, f32p]
+    lib.trs_mlp_eval.restype = ctypes.c_int32
+    lib.trs_mlp_train.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, u64p,
+                                  P(trs_train_opts), u16p, u16p, P(trs_train_result)]
+    lib.trs_mlp_train.restype = ctypes.c_int32
+    lib.trs_mlp_table.argtypes = [ctypes.c_int32, ctypes.c_int32, i32p, u16p, ctypes.c_float,
+                                  f32p, u32p]
+    lib.trs_mlp_table.restype = ctypes.c_int32
+    lib.trs_set_predictor.argtypes = [vp, u16p, ctypes.c_int64]
+    lib.trs_set_predictor.restype = ctypes.c_int32
+    lib.trs_read_trace.argtypes = [vp, u64p, ctypes.c_int64, i64p]
+    lib.trs_read_trace.restype = ctypes.c_int32
+    lib.trs_autotune.argtypes = [vp, P(trs_opts), P(trs_opts), P(trs_tune_result)]
+    lib.trs_autotune.restype = ctypes.c_int32
     return lib
 
 
@@ -194,6 +249,89 @@ def trs_device_bytes(pool_slots: int, maxarity: int) -> int:
     return int(_lib.trs_device_bytes(pool_slots, maxarity))
 
 
+def _ptr(a, ct):
+    return a.ctypes.data_as(ctypes.POINTER(ct))
+
+
+def _u16(a):
+    return np.ascontiguousarray(a, dtype=np.uint16)
+
+
+def _u64(a):
+    return np.ascontiguousarray(a, dtype=np.uint64)
+
+
+def trs_mlp_param_count(n_sym: int) -> int:
+    return int(_lib.trs_mlp_param_count(n_sym))
+
+
+def trs_mlp_eval(n_sym: int, params_bf16, records, grads: bool = True, probs: bool = False,
+                 device: int = 0):
+    """(mean loss, gradients or None, probabilities or None) on the device."""
+    w, r = _u16(params_bf16), _u64(records)
+    P = trs_mlp_param_count(n_sym)
+    loss = ctypes.c_double(0.0)
+    g = np.zeros(P, np.float32) if grads else None
+    p = np.zeros(len(r), np.float32) if probs else None
+    st = _lib.trs_mlp_eval(device, n_sym, _ptr(w, ctypes.c_uint16), len(r),
+                           _ptr(r, ctypes.c_uint64), ctypes.byref(loss),
+                           _ptr(g, ctypes.c_float) if grads else None,
+                           _ptr(p, ctypes.c_float) if probs else None)
+    if st != TRS_OK:
+        raise TRSError(st, "trs_mlp_eval")
+    return loss.value, g, p
+
+
+def trs_mlp_train(n_sym: int, records, init_bf16, epochs: int = 4, batch: int = 4096,
+                  lr: float = 3e-3, val_frac: float = 0.1, device: int = 0):
+    """(trained bfloat16 parameters, result dict)."""
+    r, w0 = _u64(records), _u16(init_bf16)
+    out = np.zeros(trs_mlp_param_count(n_sym), np.uint16)
+    o = trs_train_opts(epochs=epochs, batch=batch, lr=lr, val_frac=val_frac)
+    res = trs_train_result()
+    st = _lib.trs_mlp_train(device, n_sym, len(r), _ptr(r, ctypes.c_uint64), ctypes.byref(o),
+                            _ptr(w0, ctypes.c_uint16), _ptr(out, ctypes.c_uint16),
+                            ctypes.byref(res))
+    if st != TRS_OK:
+        raise TRSError(st, "trs_mlp_train")
+    return out, res.as_dict()
+
+
+def trs_mlp_table(arity, params_bf16, threshold: float, device: int = 0):
+    """(probabilities [n_sym, 32, 16], keep-bit words) evaluated on the device."""
+    a, ap = _i32(arity)
+    w = _u16(params_bf16)
+    n_sym = len(a)
+    probs = np.zeros(n_sym * 512, np.float32)
+    words = np.zeros(n_sym * 16, np.uint32)
+    st = _lib.trs_mlp_table(device, n_sym, ap, _ptr(w, ctypes.c_uint16), threshold,
+                            _ptr(probs, ctypes.c_float), _ptr(words, ctypes.c_uint32))
+    if st != TRS_OK:
+        raise TRSError(st, "trs_mlp_table")
+    return probs.reshape(n_sym, 32, 16), words
+
+
+def trs_set_predictor(h, params_bf16):
+    w = _u16(params_bf16)
+    _check(h, _lib.trs_set_predictor(h, _ptr(w, ctypes.c_uint16), len(w)))
+
+
+def trs_autotune(h, base: trs_opts):
+    """(best trs_opts, result dict)."""
+    best = trs_opts()
+    res = trs_tune_result()
+    _check(h, _lib.trs_autotune(h, ctypes.byref(base), ctypes.byref(best), ctypes.byref(res)))
+    return best, res.as_dict()
+
+
+def trs_read_trace(h) -> np.ndarray:
+    n = ctypes.c_int64(0)
+    _check(h, _lib.trs_read_trace(h, None, 0, ctypes.byref(n)))
+    out = np.zeros(n.value, np.uint64)
+    _check(h, _lib.trs_read_trace(h, _ptr(out, ctypes.c_uint64), len(out), ctypes.byref(n)))
+    return out[:n.value]
+
+
 # ----------------------------------------------------------- convenience
 
 @dataclass
@@ -206,11 +344,12 @@ class Options:
     threshold: float = 0.1
     persistent: int = 0
     trace: int = 0
+    trace_cap: int = 0
 
     def to_c(self) -> trs_opts:
         o = trs_default_opts()
         for k in ("mode", "block", "nodes_per_thread", "rounds_per_poll", "max_rounds",
-                  "threshold", "persistent", "trace"):
+                  "threshold", "persistent", "trace", "trace_cap"):
             setattr(o, k, getattr(self, k))
         return o
 
@@ -297,3 +436,17 @@ class Context:
 
     def rule_counts(self) -> np.ndarray:
         return trs_rule_counts(self.h, self.n_rules)
+
+    def set_predictor(self, params_bf16):
+        trs_set_predictor(self.h, params_bf16)
+
+    def read_trace(self) -> np.ndarray:
+        return trs_read_trace(self.h)
+
+    def autotune(self, opts: Options | None = None, **kw):
+        """(Options with the tuned block / nodes_per_thread, result dict)."""
+        o = opts or Options(**kw)
+        best, res = trs_autotune(self.h, o.to_c())
+        out = Options(**{k: getattr(o, k) for k in o.__dataclass_fields__})
+        out.block, out.nodes_per_thread = best.block, best.nodes_per_thread
+        return out, res

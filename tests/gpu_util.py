@@ -15,11 +15,13 @@ def say(*a):
     sys.stdout.flush()
 
 
-def run_gpu(trs, terms, pool_slots, maxarity=0, **opts):
+def run_gpu(trs, terms, pool_slots, maxarity=0, predictor=None, **opts):
     from paper_2009_07174_amd import trs as T
     ctx = T.Context(pool_slots, maxarity)
     try:
         ctx.load_trs(trs)
+        if predictor is not None:
+            ctx.set_predictor(predictor)
         ctx.load_term_list(list(terms))
         st = ctx.normalize(**opts)
         nfs = [ctx.read_nf(i) for i in range(len(terms))]
@@ -35,9 +37,9 @@ def run_oracle(trs, terms):
     return [r.nf for r in res], counts
 
 
-def assert_parity(trs, terms, pool_slots, maxarity=0, label="", **opts):
+def assert_parity(trs, terms, pool_slots, maxarity=0, label="", predictor=None, **opts):
     say(f"[parity] {label}: {len(terms)} terms, {sum(len(t) for t in terms)} nodes, opts={opts}")
-    nfs, counts, st = run_gpu(trs, terms, pool_slots, maxarity, **opts)
+    nfs, counts, st = run_gpu(trs, terms, pool_slots, maxarity, predictor=predictor, **opts)
     say(f"[parity] {label}: gpu rounds={st['rounds']} apps={st['rule_apps']} ms={st['device_ms']:.2f}")
     onfs, ocounts = run_oracle(trs, terms)
     for i, (a, b) in enumerate(zip(nfs, onfs)):

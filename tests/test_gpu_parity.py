@@ -15,7 +15,7 @@ import pytest
 from trs_workloads import generators as G
 from trs_workloads import parse_trs, systems
 from tests import closed_forms as CF
-from tests.gpu_util import assert_parity, run_gpu, say
+from tests.gpu_util import assert_parity, run_gpu, run_oracle, say
 from tests.test_oracle_pins import load_fixture
 
 pytestmark = pytest.mark.gpu
@@ -192,3 +192,26 @@ def test_repeat_normalize_same_context():
             np.testing.assert_array_equal(ctx.read_nf(0), CF.numeral_code(trs, CF.fib(n + 1)))
     finally:
         ctx.close()
+
+
+def test_autotune_picks_a_shape_and_keeps_results():
+    from paper_2009_07174_amd import trs as T
+    w = G.cfg3(120, 1 << 21, "mini")
+    ctx = T.Context(w.pool_slots, w.maxarity)
+    try:
+        ctx.load_trs(w.trs)
+        ctx.load_term_list(w.terms)
+        best, res = ctx.autotune(T.Options(mode=1))
+        say(f"[autotune] {res}")
+        assert res["trials"] == 6
+        assert (best.block, best.nodes_per_thread) == (res["best_block"], res["best_npt"])
+        assert res["best_ms"] == min(ms for _, _, ms in res["table"])
+        best2, res2 = ctx.autotune(T.Options(mode=1))   # cached
+        assert res2["trials"] == 0 and best2.block == best.block
+        ctx.normalize(best)
+        nfs = [ctx.read_nf(i) for i in range(len(w.terms))]
+    finally:
+        ctx.close()
+    onfs, _ = run_oracle(w.trs, w.terms)
+    assert all(np.array_equal(a, b) for a, b in zip(nfs, onfs))
+
