@@ -168,8 +168,11 @@ def main():
                      persistent=1 if args.persistent else 0, threshold=args.threshold)
     tune = None
     if not args.no_autotune and not args.block and not args.npt:
-        log("[bench] autotuning block and nodes per thread")
-        opts, tune = ctx.autotune(opts)
+        # the launch shape is tuned on the parent-notification frontier (six
+        # complete runs, seconds each) and used for every mode
+        log("[bench] autotuning block and nodes per thread (frontier mode)")
+        tuned, tune = ctx.autotune(T.Options(mode=T.TRS_MODE_FRONTIER, threshold=args.threshold))
+        opts.block, opts.nodes_per_thread = tuned.block, tuned.nodes_per_thread
         log(f"[bench] autotune: {tune}")
     stream = torch.cuda.current_stream()
     for i in range(args.warmup):

@@ -106,6 +106,13 @@ typedef struct {
                                 probability k/65536 (for training the
                                 predictor; the memo shortcut is off then) */
   int64_t trace_cap;         /* records kept (0 = 1<<24); later ones dropped */
+  int32_t label_horizon;     /* tracing: a record is labelled 1 when its node
+                                fires or becomes a normal form within this
+                                many rounds (1 = the next round; 0 = 8) */
+  int32_t sweep_every;       /* learned mode: also sweep every slot every k
+                                rounds, so that a node the predictor drops
+                                waits at most k rounds (0 = 8; -1 = only
+                                when the frontier is empty or a round stalls) */
 } trs_opts;
 
 typedef struct {
@@ -219,9 +226,10 @@ trs_status trs_membench(int32_t device, trs_membench_result *out);
 /* ------------------------------------------------------------------------
  * Frontier predictor (TRS_MODE_LEARNED).  Not part of the paper: a small
  * network that predicts, for a node found blocked in a round (an argument
- * not yet a normal form), whether it will be able to fire or become a normal
- * form in the next round; only nodes it keeps are examined then, and a full
- * sweep still confirms the normal form (so results stay exact).
+ * not yet a normal form), whether it will fire or become a normal form soon
+ * (within the label horizon); only nodes it keeps are examined in the next
+ * round, the others at the next full sweep (every sweep_every rounds), and a
+ * full sweep still confirms the normal form (so results stay exact).
  *
  *   x  = [E[sym] (16), arity/8, c_0..c_4, bucket(age)/15, 0]       (24)
  *   h1 = relu(W1 x + b1) (32);  h2 = relu(W2 h1 + b2) (32)
@@ -235,7 +243,9 @@ trs_status trs_membench(int32_t device, trs_membench_result *out);
  *
  * Trace record (uint64, written by trs_normalize with trs_opts.trace > 0):
  * sym bits 0-15, arity 16-19, c_0..c_4 bits 20-24, age bucket 25-28, label
- * bit 32 (1: the node fired or became a normal form in the next round).
+ * bit 32 (1: the node fired or became a normal form within
+ * trs_opts.label_horizon rounds; a node's later record supersedes its
+ * earlier one).
  * ------------------------------------------------------------------------ */
 #define TRS_MLP_EMB 16
 #define TRS_MLP_DIN 24

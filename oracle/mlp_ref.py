@@ -23,7 +23,8 @@ min(15, floor(log2 a) + 1) for a >= 1, so the input space is finite:
 
 Trace record (one uint64 per sampled node-round): symbol in bits 0-15, arity
 in bits 16-19, c_0..c_4 in bits 20-24, age bucket in bits 25-28, label in
-bit 32 (1 when the node fired or became a normal form in the next round).
+bit 32 (1 when the node fired or became a normal form within the label
+horizon, a number of rounds).
 Weights are stored in bfloat16; the reference takes them already rounded
 (float64 values exactly representable in bfloat16) so that it evaluates the
 same function as the GPU, whose arithmetic accumulates in float32.

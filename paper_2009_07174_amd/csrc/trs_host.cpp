@@ -466,6 +466,8 @@ void trs_default_opts(trs_opts *o) {
   o->persistent = 0;
   o->trace = 0;
   o->trace_cap = 0;
+  o->label_horizon = 0;
+  o->sweep_every = 0;
 }
 
 trs_status trs_create(trs_ctx **out, const trs_config *cfg) {
@@ -678,6 +680,8 @@ trs_status trs_normalize(trs_ctx *c, const trs_opts *opts_in, trs_stats *stats) 
       return c->fail(TRS_E_ARG, "threshold must be in [0, 1]");
   }
   if (o.trace < 0 || o.trace > 65536) return c->fail(TRS_E_ARG, "trace rate must be 0..65536");
+  if (o.label_horizon < 0 || o.sweep_every < -1)
+    return c->fail(TRS_E_ARG, "label_horizon must be >= 0, sweep_every >= -1");
   if (o.trace && o.mode != TRS_MODE_PLAIN)
     return c->fail(TRS_E_ARG, "traces are logged by plain-mode runs");
   const int64_t tcap = o.trace_cap ? o.trace_cap : ((int64_t)1 << 24);
@@ -808,8 +812,10 @@ trs_status trs_normalize(trs_ctx *c, const trs_opts *opts_in, trs_stats *stats) 
   ra.tab = c->d_tab;
   ra.tab_words = gate_words ? gate_off + gate_words : (int32_t)c->tab.size();
   ra.gate_off = gate_off;
-  ra.use_memo = (o.mode != TRS_MODE_LEARNED && !o.trace) ? 1 : 0;
+  ra.use_memo = o.trace ? 0 : 1;
+  ra.sweep_every = o.mode == TRS_MODE_LEARNED ? (o.sweep_every == 0 ? 8 : std::max(0, o.sweep_every)) : 0;
   if (o.trace) {
+    ra.label_h = o.label_horizon > 0 ? o.label_horizon : 8;
     ra.trace_rate = (uint32_t)o.trace;
     ra.trace_cap_rec = tcap;
     ra.trace_rec = c->d_trace_rec;
@@ -859,6 +865,10 @@ trs_status trs_normalize(trs_ctx *c, const trs_opts *opts_in, trs_stats *stats) 
   ra.cont_rounds = o.max_rounds > 0 ? (int)std::min<int64_t>(o.max_rounds + 1, 4096) : 4096;
   HIPCHK(c, hipEventRecord(c->ev0, s));
   const size_t small = offsetof(Ctl, stat);  // control words and round counters
+  // opt-in progress lines on stderr for long runs (TRS_PROGRESS set)
+  const bool progress = std::getenv("TRS_PROGRESS") != nullptr;
+  const auto t_start = std::chrono::steady_clock::now();
+  double last_report = 0.0;
   int64_t front_est = 0;
   trs_status result = TRS_OK;
   for (;;) {
@@ -912,6 +922,14 @@ trs_status trs_normalize(trs_ctx *c, const trs_opts *opts_in, trs_stats *stats) 
     HIPCHK(c, hipMemcpyAsync(c->h_ctl, c->d_ctl, small, hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));
     r = c->h_ctl->r_cur;
+    if (progress) {
+      const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+      if (el - last_report >= 10.0) {
+        std::fprintf(stderr, "[trs] round %lld, extent %d, %.0f s\n", (long long)r,
+                     c->h_ctl->peak_n, el);
+        last_report = el;
+      }
+    }
     if (c->h_ctl->abort) {
       result = c->fail(TRS_E_INTERNAL, "device-wide barrier timed out");
       break;

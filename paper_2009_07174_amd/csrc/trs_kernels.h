@@ -24,6 +24,8 @@ struct RoundArgs {
   uint32_t trace_rate;  // tracing: keep a blocked node-round when its hash
                         // (16 bits) is below this; 0 = off
   int64_t trace_cap_rec;     // records the buffer holds
+  int32_t label_h;      // tracing: label horizon in rounds
+  int32_t sweep_every;  // learned mode: full sweep every k rounds (0: never)
   unsigned long long *trace_rec;  // trace records
   int32_t *trace_n;     // records logged so far
   unsigned long long *bar;  // grid barrier counter (persistent kernel)
@@ -33,9 +35,11 @@ struct RoundArgs {
 
 // Phase timestamps (clock64) recorded by thread 0 of workgroup 0 per round:
 // prepare start, prepare end, bookkeeping end, list phase end, sweep end,
-// statistics end, and inside the first list pass: readiness checked,
-// matched, reserved, instantiated, flushed.
-#define TRACE_FIELDS 12
+// statistics end; inside the first list pass: readiness checked, matched,
+// reserved, instantiated, flushed (11 fields); then, for the workgroup's
+// first sweep tile: bytes loaded, slots classified, work list appended,
+// work passes done.
+#define TRACE_FIELDS 16
 
 // LDS bytes a round kernel needs for this configuration.
 size_t trs_round_lds_bytes(int block, int npt, int tab_words, int n_rules);

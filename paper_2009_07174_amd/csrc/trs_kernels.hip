@@ -123,6 +123,8 @@ struct Lds {
   //       [63] barrier flag
   int32_t *misc;
   int32_t *rcnt;  // per-rule application counts of this workgroup
+  uint4 *pf;      // sweep prefetch: 16 state bytes ([0, B)) and 16 wake bytes
+                  // ([B, 2B)) per thread for the next tile
   // statistics of this workgroup over every round it runs in the launch,
   // flushed once at the end of the launch: STAT_* then gc rounds, full
   // sweeps, peak extent
@@ -272,6 +274,33 @@ __device__ __forceinline__ void notify_parent(const RoundArgs &a, const Lds &L, 
   }
 }
 
+typedef __attribute__((address_space(3))) void lds_void;
+
+// Asynchronous copy of 16 bytes per lane from global memory straight into
+// LDS (no registers held while in flight): lane l of the wave writes
+// dst_wave[l], where dst_wave is the wave's (uniform) base.
+__device__ __forceinline__ void lds_fetch16(const void *src, uint4 *dst_wave) {
+  __builtin_amdgcn_global_load_lds(src, (lds_void *)dst_wave, 16, 0, 0);
+}
+
+// npt (1, 2, 4, 8 or 16) consecutive bytes, in byte order from the low end
+// of a uint4 (the rest zero); one vector load for 4, 8 and 16
+__device__ __forceinline__ uint4 load_bytes(const uint8_t *q, int npt) {
+  uint4 v = make_uint4(0, 0, 0, 0);
+  if (npt == 16) {
+    v = *reinterpret_cast<const uint4 *>(q);
+  } else if (npt == 8) {
+    const uint2 u = *reinterpret_cast<const uint2 *>(q);
+    v.x = u.x;
+    v.y = u.y;
+  } else if (npt == 4) {
+    v.x = *reinterpret_cast<const uint32_t *>(q);
+  } else {
+    for (int j = 0; j < npt; j++) v.x |= (unsigned)q[j] << (8 * j);
+  }
+  return v;
+}
+
 // Bit 0 of each byte of x, packed into bits 0-3 (the four products land on
 // distinct bit positions, so no carries mix them).
 __device__ __forceinline__ int pack4(unsigned x) {
@@ -345,27 +374,34 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
             if (j >= ar || (j < A && nf_visible(p.state[av[j]], e))) bits |= 1 << j;
           ready = bits == 31;
           if (!ready) {
-            if (a.use_memo) {
+            // learned mode sets the memo only for nodes the predictor drops
+            if (a.use_memo && R.mode != 2) {
               const int first_blocked = __builtin_ctz(~bits) + 1;
               if (first_blocked != memo)
                 p.state[s] = (uint8_t)(ST_ACTIVE | (first_blocked << ST_MEMO_SHIFT));
-            } else {
-              nfb = bits;
             }
+            nfb = bits;
           }
         }
       }
     }
   }
-  if (nfb >= 0) {
-    // a blocked node without the memo shortcut: learned mode asks the
+  if (nfb >= 0 && (R.mode == 2 || a.trace_rate)) {
+    // a blocked node after a full readiness test: learned mode asks the
     // predictor whether to examine it again next round; tracing samples it
     const int bk = age_bucket(R.r - p.lastchg[s]);
     if (R.mode == 2) {
+      // kept: examined next round (no memo, so a full sweep tests it in
+      // full too); dropped: sleeps on its first blocking argument until a
+      // full sweep finds that argument in normal form
       C.mlp++;
+      const int fb = __builtin_ctz(~nfb) + 1;
       if (gate_keep(L, a.gate_off, f, nfb, bk)) {
         C.keep++;
         qpush(L, L.qf, s, N);
+        if (memo) p.state[s] = (uint8_t)ST_ACTIVE;
+      } else if (fb != memo) {
+        p.state[s] = (uint8_t)(ST_ACTIVE | (fb << ST_MEMO_SHIFT));
       }
     } else if (a.trace_rate) {
       const uint32_t h = mix32((uint32_t)s * 0x9E3779B1u ^ (uint32_t)R.r * 0x85EBCA77u);
@@ -382,11 +418,12 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
     }
   }
   if (ready && a.trace_rate && R.r > 0) {
-    // label of the node's record from the previous round: it can fire or
-    // become a normal form now
+    // label of the node's latest record, when it was logged at most
+    // label_h rounds ago: the node fires or becomes a normal form now
     const long long t = p.tref[s];
     const long long idx = t >> 32;
-    if ((int)(t & 0xffffffff) == R.r - 1 && idx >= 0 && idx < a.trace_cap_rec)
+    const int rr = (int)(t & 0xffffffff);  // round of the record
+    if (rr >= 0 && rr < R.r && R.r - rr <= a.label_h && idx >= 0 && idx < a.trace_cap_rec)
       a.trace_rec[idx] |= 1ull << 32;
   }
   tmark(a, R.r, 6);
@@ -579,6 +616,8 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
             C.mlp++;
             keep = gate_keep(L, a.gate_off, rsym, bits, 0);
             C.keep += keep;
+            if (!keep)  // sleeps on its first argument not in normal form
+              p.state[s] = (uint8_t)(ST_ACTIVE | ((__builtin_ctz(~bits) + 1) << ST_MEMO_SHIFT));
           }
           if (keep) qpush(L, L.qf, s, N);
         }
@@ -729,7 +768,8 @@ __device__ __forceinline__ RoundState round_state(const RoundArgs &a, int r) {
   rs.stall = stall;
   rs.err = err;
   rs.done = false;
-  rs.full = !quiescent && (a.mode == 0 || nfront == 0 || r == 0 || stall);
+  rs.full = !quiescent && (a.mode == 0 || nfront == 0 || r == 0 || stall ||
+                           (a.sweep_every > 0 && r % a.sweep_every == 0));
   // in full rounds the sweep retires every marker, so the retire list is
   // skipped
   rs.nlist = nd + (rs.full ? 0 : nret + nfront);
@@ -792,7 +832,8 @@ __device__ __forceinline__ RoundState round_prepare(const RoundArgs &a, const Ld
   rs.err = bc[9] >> 8;
   __syncthreads();
   tmark(a, rs.r, 0);
-  rs.full = !rs.quiescent && (a.mode == 0 || rs.nfront == 0 || rs.r == 0 || rs.stall);
+  rs.full = !rs.quiescent && (a.mode == 0 || rs.nfront == 0 || rs.r == 0 || rs.stall ||
+                              (a.sweep_every > 0 && rs.r % a.sweep_every == 0));
   rs.nlist = rs.nd + (rs.full ? 0 : rs.nret + rs.nfront);
   rs.ntiles = rs.full ? (rs.n + B * a.npt - 1) / (B * a.npt) : 0;
   rs.need = max((rs.nlist + B - 1) / B, rs.ntiles);
@@ -898,7 +939,9 @@ __device__ __forceinline__ void round_execute(const RoundArgs &a, Lds &L, const 
           }
           if ((st & ST_ACTIVE) && !(st & ST_PEND)) {
             s = x;
-            memo = a.use_memo ? (int)((st & ST_MEMO_MASK) >> ST_MEMO_SHIFT) : 0;
+            // (learned mode: a kept node gets the full test, so that the
+            // predictor sees all of its arguments)
+            memo = (a.use_memo && R.mode != 2) ? (int)((st & ST_MEMO_MASK) >> ST_MEMO_SHIFT) : 0;
           }
         }
       }
@@ -913,25 +956,44 @@ __device__ __forceinline__ void round_execute(const RoundArgs &a, Lds &L, const 
     const int TILE = B * npt;
     const unsigned e = R.e;
     const bool wake_sweep = a.mode == 0 && a.use_memo && !rs.stall;
-    for (int t = xcd_remap(wg, Ga); t < ntiles; t += Ga) {
+    // with 16 slots per thread, the state (and in plain mode wake) bytes of
+    // the next tile are copied into LDS while the current tile is worked
+    // on (the bytes of a later tile cannot change meanwhile in a way that
+    // matters: collection is over, and slots that become live this round
+    // carry this round's marker)
+    const bool ahead = npt == 16;
+    int t = xcd_remap(wg, Ga);
+    const int t_first = t;
+    if (ahead && t < ntiles) {
+      const int64_t b0 = (int64_t)t * TILE + tid * 16;
+      lds_fetch16(p.state + b0, L.pf + (tid & ~63));  // this wave's entries
+      if (wake_sweep) lds_fetch16(p.wake + b0, L.pf + B + (tid & ~63));
+    }
+    for (; t < ntiles; t += Ga) {
       const int base = t * TILE + tid * npt;
-      // state bytes of this thread's slots, kept in four registers
-      ivec4 sw = (ivec4)(0);
-      if (npt == 16) {
-        const uint4 v = *reinterpret_cast<const uint4 *>(p.state + base);
-        sw[0] = (int)v.x;
-        sw[1] = (int)v.y;
-        sw[2] = (int)v.z;
-        sw[3] = (int)v.w;
-      } else if (npt == 8) {
-        const uint2 v = *reinterpret_cast<const uint2 *>(p.state + base);
-        sw[0] = (int)v.x;
-        sw[1] = (int)v.y;
-      } else if (npt == 4) {
-        sw[0] = (int)*reinterpret_cast<const uint32_t *>(p.state + base);
+      uint4 vs, vw = make_uint4(0, 0, 0, 0);
+      if (ahead) {
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        vs = L.pf[tid];
+        if (wake_sweep) vw = L.pf[B + tid];
+        // the entries are read before the next tile's copy overwrites them
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+        if (t + Ga < ntiles) {
+          const int64_t nb = (int64_t)(t + Ga) * TILE + tid * 16;
+          lds_fetch16(p.state + nb, L.pf + (tid & ~63));
+          if (wake_sweep) lds_fetch16(p.wake + nb, L.pf + B + (tid & ~63));
+        }
       } else {
-        for (int j = 0; j < npt; j++) sw[0] |= (int)p.state[base + j] << (8 * j);
+        vs = load_bytes(p.state + base, npt);
+        if (wake_sweep) vw = load_bytes(p.wake + base, npt);
       }
+      if (t == t_first) tmark(a, r, 12);
+      // state bytes of this thread's slots, kept in four registers
+      ivec4 sw;
+      sw[0] = (int)vs.x;
+      sw[1] = (int)vs.y;
+      sw[2] = (int)vs.z;
+      sw[3] = (int)vs.w;
       // plain mode: the wake bits of the same slots, for the parity of the
       // previous rounds, packed into a 16-bit mask (a sleeping slot -- one
       // with a memo -- is tested again only once an argument has become a
@@ -939,18 +1001,9 @@ __device__ __forceinline__ void round_execute(const RoundArgs &a, Lds &L, const 
       int wmask = 0;
       if (wake_sweep) {
         const unsigned sh = 1u - e;
-        if (npt == 16) {
-          const uint4 v = *reinterpret_cast<const uint4 *>(p.wake + base);
-          wmask = pack4(v.x >> sh) | pack4(v.y >> sh) << 4 | pack4(v.z >> sh) << 8 |
-                  pack4(v.w >> sh) << 12;
-        } else if (npt == 8) {
-          const uint2 v = *reinterpret_cast<const uint2 *>(p.wake + base);
-          wmask = pack4(v.x >> sh) | pack4(v.y >> sh) << 4;
-        } else if (npt == 4) {
-          wmask = pack4(*reinterpret_cast<const uint32_t *>(p.wake + base) >> sh);
-        } else {
-          for (int j = 0; j < npt; j++) wmask |= (int)((p.wake[base + j] >> sh) & 1u) << j;
-        }
+        wmask = pack4(vw.x >> sh) | pack4(vw.y >> sh) << 4 | pack4(vw.z >> sh) << 8 |
+                pack4(vw.w >> sh) << 12;
+        if (npt < 16) wmask &= (1 << npt) - 1;
       }
       // classify the thread's slots; otherwise, for live slots with a memo,
       // read the recorded argument of all of them first, then all their
@@ -981,8 +1034,9 @@ __device__ __forceinline__ void round_execute(const RoundArgs &a, Lds &L, const 
       int cst[16];
 #pragma unroll
       for (int j = 0; j < 16; j++) cst[j] = (pending >> j & 1) && cidx[j] ? p.state[cidx[j]] : 0;
-      // compact the slots to examine into the LDS work list (the loop is
-      // uniform: every lane takes part in each wave-wide reservation)
+      if (t == t_first) tmark(a, r, 13);
+      // the slots of this thread to examine
+      int exam = 0;
 #pragma unroll
       for (int j = 0; j < 16; j++) {
         if (j >= npt) break;
@@ -1002,20 +1056,44 @@ __device__ __forceinline__ void round_execute(const RoundArgs &a, Lds &L, const 
         }
         C.active += live;
         C.memo += still;  // still blocked by the same argument
-        const int w = wave_reserve(live && !still, &L.misc[0]);
-        if (w >= 0) L.work[w] = (base + j) | (memo << 29);
+        if (live && !still) exam |= 1 << j;
+      }
+      // append them to the LDS work list: a wave prefix sum of the counts
+      // and one LDS atomic per wave
+      {
+        const int cnt = __popc(exam);
+        const int incl = wave_incl_scan(cnt);
+        const int tot = __shfl(incl, 63, 64);
+        int wb = 0;
+        if (lane() == 63 && tot) wb = atomicAdd(&L.misc[0], tot);
+        int pos = __shfl(wb, 63, 64) + incl - cnt;
+        for (int m = exam; m; m &= m - 1) {
+          const int j = __builtin_ctz(m);
+          const unsigned byte = ((unsigned)sw[j >> 2] >> ((j & 3) * 8)) & 0xffu;
+          const int memo = ((byte & ST_PEND) || !a.use_memo)
+                               ? 0
+                               : (int)((byte & ST_MEMO_MASK) >> ST_MEMO_SHIFT);
+          L.work[pos++] = (base + j) | (memo << 29);
+        }
       }
       __syncthreads();
-      const int W = L.misc[0];
-      for (int pb = 0; pb < W; pb += B) {
-        const int idx = pb + tid;
-        const int wv = idx < W ? L.work[idx] : 0;
+      int W = L.misc[0];
+      __syncthreads();  // every thread has read the count before it changes
+      if (t == t_first) tmark(a, r, 14);
+      // examine in full passes of B slots while at least B are waiting; the
+      // rest carries over to the next tile (the list holds a tile plus B),
+      // and after the last tile everything is examined
+      const bool last = t + Ga >= ntiles;
+      while (W >= B || (last && W > 0)) {
+        const int take = min(W, B);
+        const int wv = tid < take ? L.work[W - take + tid] : 0;
+        __syncthreads();
+        if (tid == 0) L.misc[0] = W - take;
         process_slot<A>(a, L, R, wv & 0x1fffffff, (int)((unsigned)wv >> 29), true, 0, SQ, fsQ,
                         C);
+        W -= take;
       }
-      __syncthreads();
-      if (tid == 0) L.misc[0] = 0;
-      __syncthreads();
+      if (t == t_first) tmark(a, r, 15);
     }
   }
 
@@ -1085,7 +1163,7 @@ __device__ __forceinline__ Lds setup_lds(const RoundArgs &a, int32_t *smem, bool
   const int B = blockDim.x;
   L.tab = smem;
   L.work = L.tab + ((a.tab_words + 3) & ~3);
-  int32_t *q = L.work + B * a.npt;
+  int32_t *q = L.work + B * a.npt + B;  // a tile's slots plus a carried-over pass
   const int qc = QBUF_PER_THREAD * B;
   L.qd.buf = q;
   L.qf.buf = q + qc;
@@ -1094,7 +1172,8 @@ __device__ __forceinline__ Lds setup_lds(const RoundArgs &a, int32_t *smem, bool
   L.qd.slot = 1;
   L.qf.slot = 2;
   L.qr.slot = 3;
-  L.misc = q + 3 * qc;
+  L.pf = reinterpret_cast<uint4 *>(q + 3 * qc);
+  L.misc = q + 3 * qc + 8 * B;
   L.lstat = reinterpret_cast<unsigned long long *>(L.misc + 64);
   L.rcnt = L.misc + 64 + 2 * 16;
   if (load_tab)
@@ -1130,12 +1209,16 @@ __global__ void __launch_bounds__(1024) k_round(RoundArgs a) {
   Ctl *ctl = a.ctl;
   Lds L = setup_lds(a, smem, false);  // tables are loaded only by workgroups with work
   const int wg = blockIdx.x, tid = threadIdx.x;
-  // the first round of this launch, as published by the previous launch;
-  // workgroups beyond the number it uses leave without reading any round
-  // counter (workgroup 0 may already be running later rounds alone)
+  // the first round of this launch, as published by the previous launch.
+  // Workgroups beyond the number it uses leave at once, without reading any
+  // round counter (workgroup 0 may be running later rounds alone) and
+  // without a ticket, so a launch costs as many control atomics as
+  // workgroups at work, however large its grid.
   RoundState rs = round_prepare(a, L, 0, true);
   if (rs.done) return;
-  if (wg < rs.need) {
+  const int need0 = rs.need;
+  if (wg >= need0) return;
+  {
     if (rs.stop) {
       if (wg == 0 && tid == 0) round_stop(a, rs);
       return;
@@ -1164,8 +1247,9 @@ __global__ void __launch_bounds__(1024) k_round(RoundArgs a) {
   if (tid == 0) {
     __threadfence();
     const int t = atomicAdd(&ctl->ticket, 1);
-    if (t == (int)gridDim.x - 1) {
-      // last workgroup of the launch: every round it covered is complete
+    if (t == min(need0, (int)gridDim.x) - 1) {
+      // last working workgroup of the launch: every round it covered is
+      // complete
       __threadfence();
       const int rr = max(ld(&ctl->r_cur) + 1, ld(&ctl->r_reached));
       const RoundState nx = round_state(a, rr);
@@ -1244,8 +1328,9 @@ __global__ void __launch_bounds__(1024) k_persistent(RoundArgs a) {
 }  // namespace
 
 size_t trs_round_lds_bytes(int block, int npt, int tab_words, int n_rules) {
-  size_t words = (size_t)((tab_words + 3) & ~3) + (size_t)block * npt +
-                 (size_t)3 * QBUF_PER_THREAD * block + 64 + 2 * 16 + (size_t)n_rules;
+  size_t words = (size_t)((tab_words + 3) & ~3) + (size_t)block * npt + block +
+                 (size_t)3 * QBUF_PER_THREAD * block + (size_t)8 * block + 64 + 2 * 16 +
+                 (size_t)n_rules;
   return words * sizeof(int32_t);
 }
 

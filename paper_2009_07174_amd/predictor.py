@@ -3,8 +3,10 @@
 * Training data are trace records logged on the device by plain-mode runs
   (``trs_opts.trace``): for a sampled node found blocked in round r, its head
   symbol, arity, which arguments are normal forms, and how long ago it last
-  changed; the label says whether it fired or became a normal form in round
-  r + 1.
+  changed; the label says whether it fired or became a normal form within
+  the next few rounds (the label horizon; the same number of rounds is the
+  learned mode's sweep period, so a node the predictor drops waits at most
+  that long).
 * Training runs on the device (``trs_mlp_train``: the library's forward,
   backward and Adam kernels).
 * Parameters are stored as ``.npz`` (uint16 bfloat16 bit patterns plus the

@@ -38,7 +38,8 @@ class trs_opts(ctypes.Structure):
                 ("nodes_per_thread", ctypes.c_int32), ("rounds_per_poll", ctypes.c_int32),
                 ("max_rounds", ctypes.c_int64), ("threshold", ctypes.c_float),
                 ("persistent", ctypes.c_int32), ("trace", ctypes.c_int32),
-                ("trace_cap", ctypes.c_int64)]
+                ("trace_cap", ctypes.c_int64), ("label_horizon", ctypes.c_int32),
+                ("sweep_every", ctypes.c_int32)]
 
 
 class trs_stats(ctypes.Structure):
@@ -104,6 +105,13 @@ EXPORTS = ["trs_create", "trs_destroy", "trs_load_rules", "trs_load_terms", "trs
 
 
 def _load_lib():
+    # PyTorch brings its own HIP runtime; importing it first makes that the
+    # one the library binds to, so that both share devices, memory and
+    # streams in one process
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with "
                           "`python -m paper_2009_07174_amd.build`")
@@ -345,11 +353,14 @@ class Options:
     persistent: int = 0
     trace: int = 0
     trace_cap: int = 0
+    label_horizon: int = 0
+    sweep_every: int = 0
 
     def to_c(self) -> trs_opts:
         o = trs_default_opts()
         for k in ("mode", "block", "nodes_per_thread", "rounds_per_poll", "max_rounds",
-                  "threshold", "persistent", "trace", "trace_cap"):
+                  "threshold", "persistent", "trace", "trace_cap", "label_horizon",
+                  "sweep_every"):
             setattr(o, k, getattr(self, k))
         return o
 

@@ -61,7 +61,7 @@ def test_trace_records_of_a_tiny_term():
     try:
         ctx.load_trs(trs)
         ctx.load_term_list([term])
-        st = ctx.normalize(mode=0, trace=65536)
+        st = ctx.normalize(mode=0, trace=65536, label_horizon=1)
         rec = ctx.read_trace()
         nf = ctx.read_nf(0)
     finally:
