@@ -13,11 +13,12 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cfg3]
 
 The default workload is the batched configuration: 4096 independent terms
 (plus/times trees, g(S^n(0)) and merge sorts in equal parts) in one 2^27-slot
-pool, whose full sweeps exceed the 256 MB Infinity Cache.  The default mode
-is the learned frontier (the predictor's parameters come from --weights, or
-are trained on the device first, outside the timed region); the same
-workload is also run once in each --compare mode and reported under
-``compare`` (plain vs learned frontier).  The printed JSON line carries a
+pool, whose full sweeps exceed the 256 MB Infinity Cache.  The timed mode is
+the parent-notification frontier; the same workload is also run once in each
+--compare mode and reported under ``compare``: the plain sweep (the paper's
+method) and the learned frontier (the predictor's parameters come from
+--weights or the packaged file, else they are trained on the device first,
+outside the timed region).  The printed JSON line carries a
 ``roofline`` object for the round kernel (algorithmic bytes of the run /
 device time of the round loop, against 8 TB/s) and a ``cpu_baseline``
 object: the CPU oracle timed on a bounded sample of the same workload on one
@@ -100,6 +101,44 @@ def load_predictor(w, path):
     return params
 
 
+KERNEL_SOURCES = ["paper_2009_07174_amd/csrc/trs_kernels.hip",
+                  "paper_2009_07174_amd/csrc/trs_layout.h",
+                  "paper_2009_07174_amd/csrc/trs_kernels.h"]
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str, mode: str, block: int, npt: int):
+    """HBM bytes per launch of the round kernel from the committed counter
+    summary (profiles/*.md, a fenced json block): FETCH_SIZE and WRITE_SIZE
+    per launch, each scaled by what the counter reads for a copy of known
+    size.  None unless the summary was taken on this workload, mode and
+    launch shape with the current kernel source."""
+    import glob
+    import re
+    for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        m = re.search(r"```json\n(.*?)\n```", open(f).read(), re.S)
+        if not m:
+            continue
+        try:
+            d = json.loads(m.group(1))
+        except ValueError:
+            continue
+        if (d.get("workload"), d.get("mode"), d.get("block"), d.get("npt")) != (workload, mode, block, npt):
+            continue
+        if d.get("source_sha256") != kernel_source_hash():
+            return None
+        return d["fetch_bytes_per_launch"] + d["write_bytes_per_launch"]
+    return None
+
+
 def cpu_baseline(w, budget_s: float = 15.0):
     """The oracle, as it stands, on a bounded sample of the same workload:
     terms in a fixed seeded order until about budget_s of normalisation time
@@ -130,8 +169,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cfg3")
-    ap.add_argument("--mode", default="learned", choices=["plain", "frontier", "learned"])
-    ap.add_argument("--compare", default="plain,frontier",
+    ap.add_argument("--mode", default="frontier", choices=["plain", "frontier", "learned"])
+    ap.add_argument("--compare", default="plain,learned",
                     help="comma-separated modes run once more for comparison ('' = none)")
     ap.add_argument("--weights", default=None, help="predictor parameters (.npz)")
     ap.add_argument("--threshold", type=float, default=0.1)
@@ -148,6 +187,7 @@ def main():
               "which is not built.", file=sys.stderr)
         sys.exit(2)
 
+    os.environ.setdefault("TRS_PROGRESS", "1")  # round progress on stderr in long runs
     import torch
     from paper_2009_07174_amd import trs as T
 
@@ -234,7 +274,10 @@ def main():
         "rc_atomics_per_s": st["rc_atomics"] * args.steps / wall,
         "algorithmic_bytes": ab,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
+                     "traffic": measured_traffic(w.name, args.mode, opts.block, opts.nodes_per_thread),
+                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                                     "copy-calibrated)",
                      "kernel": "k_round", "launches_per_step": st["launches"],
                      "bytes_per_launch": ab["total"] / max(st["launches"], 1),
                      "avg_launch_us": 1e3 * ev_ms_step / max(st["launches"], 1)},
@@ -258,7 +301,16 @@ def main():
                 "value": sm["rule_apps"] / wm, "ms_per_step": 1e3 * wm, "rounds": sm["rounds"],
                 "node_visits": sm["node_visits"], "node_visits_per_s": sm["node_visits"] / wm,
                 "full_sweeps": sm["full_sweeps"], "speedup_of_" + args.mode: wm / (wall / args.steps),
-                "algorithmic_gbps": algorithmic_bytes(sm, A)["total"] / wm / 1e9}
+                "algorithmic_gbps": algorithmic_bytes(sm, A)["total"] / wm / 1e9,
+                "roofline_frac": algorithmic_bytes(sm, A)["total"] / wm / 1e9 / HBM_PEAK_GBPS}
+    if compare:
+        # speedups over the plain sweep (the paper's method), from the time
+        # of one normalisation in each mode
+        times = {args.mode: wall / args.steps}
+        times.update({m: v["ms_per_step"] / 1e3 for m, v in res["compare"].items()})
+        if "plain" in times:
+            res["speedup_over_plain"] = {m: times["plain"] / t for m, t in times.items()
+                                         if m != "plain"}
     if not args.no_cpu_baseline:
         log("[bench] CPU baseline (oracle, one core)")
         res["cpu_baseline"] = cpu_baseline(w)

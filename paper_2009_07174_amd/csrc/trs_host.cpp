@@ -873,11 +873,12 @@ trs_status trs_normalize(trs_ctx *c, const trs_opts *opts_in, trs_stats *stats) 
   trs_status result = TRS_OK;
   for (;;) {
     int g = grid_for(n_est);
-    if (o.mode != TRS_MODE_PLAIN && front_est > 0) {
+    if (o.mode == TRS_MODE_FRONTIER && front_est > 0) {
       // frontier rounds need only as many workgroups as queued items (twice
       // the last observed count, as a power of two); the rare full sweeps
       // stride over all tiles with the same grid.  A persistent grid also
-      // pays its device-wide barrier per workgroup.
+      // pays its device-wide barrier per workgroup.  (Learned mode keeps the
+      // full grid: its periodic sweeps are frequent.)
       int64_t need = std::max<int64_t>(8, (2 * front_est + B - 1) / B);
       int64_t gg = 1;
       while (gg < need) gg <<= 1;
