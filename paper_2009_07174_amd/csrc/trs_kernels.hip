@@ -301,10 +301,18 @@ __device__ __forceinline__ uint4 load_bytes(const uint8_t *q, int npt) {
   return v;
 }
 
+// Bit j (j = 0..3) set when byte j of x has any of its low 7 bits set: the
+// add carries into bit 7 of the byte exactly then, and never across bytes.
+__device__ __forceinline__ int nz7x4(unsigned x);
+
 // Bit 0 of each byte of x, packed into bits 0-3 (the four products land on
 // distinct bit positions, so no carries mix them).
 __device__ __forceinline__ int pack4(unsigned x) {
   return (int)((((x & 0x01010101u) * 0x01020408u) >> 24) & 0xFu);
+}
+
+__device__ __forceinline__ int nz7x4(unsigned x) {
+  return pack4(((x & 0x7f7f7f7fu) + 0x7f7f7f7fu) >> 7);
 }
 
 // Plain mode: tell the parent of a node that just became a normal form to
@@ -338,19 +346,20 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
   bool have = s > 0;
   int info = 0, ar = 0, f = 0;
   ivec8 av = (ivec8)(0);
+  ivec8 ch = (ivec8)(-1);  // argument symbols (read with the argument states)
   bool ready = false;
   int nfb = -1;  // >= 0: the slot was examined and is blocked; bit j set when
                  // argument j is a visible normal form or j >= arity
   if (have) {
     if (!memo_checked) C.active++;
-    bool blocked = false;
-    if (memo && !memo_checked) {  // the argument that blocked the node last time
-      const int c = p.args[(int64_t)s * A + (memo - 1)];
-      if ((unsigned)c < (unsigned)N && c != 0) blocked = !nf_visible(p.state[c], e);
-      C.memo += blocked;
-    }
-    if (!blocked) {
-      f = p.hss[s];
+    // the symbol and all A argument entries are read together (entries past
+    // the arity lie within the slot's stride and are ignored), then the
+    // states and symbols of the arguments together: two dependent levels
+    f = p.hss[s];
+    ivec8 raw = (ivec8)(0);
+#pragma unroll
+    for (int j = 0; j < A; j++) raw[j] = p.args[(int64_t)s * A + j];
+    {
       if ((unsigned)f >= (unsigned)a.n_sym) {
         cnt->err = -9;
       } else {
@@ -360,7 +369,7 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
 #pragma unroll
         for (int j = 0; j < A; j++) {
           if (j < ar) {
-            const int c = p.args[(int64_t)s * A + j];
+            const int c = raw[j];
             if ((unsigned)c >= (unsigned)N || c == 0) ok = false;
             av[j] = c;
           }
@@ -370,8 +379,15 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
         } else {
           int bits = 0;
 #pragma unroll
-          for (int j = 0; j < 5; j++)
-            if (j >= ar || (j < A && nf_visible(p.state[av[j]], e))) bits |= 1 << j;
+          for (int j = 0; j < 5; j++) {
+            if (j >= ar) {
+              bits |= 1 << j;
+            } else if (j < A) {
+              const unsigned st = p.state[av[j]];
+              ch[j] = p.hss[av[j]];
+              if (nf_visible(st, e)) bits |= 1 << j;
+            }
+          }
           ready = bits == 31;
           if (!ready) {
             // learned mode sets the memo only for nodes the predictor drops
@@ -437,10 +453,6 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
     if (nr == 0) {
       nfset = true;
     } else {
-      ivec8 ch = (ivec8)(-1);
-#pragma unroll
-      for (int j = 0; j < A; j++)
-        if (j < ar) ch[j] = p.hss[av[j]];
       const int32_t *rtab = tab + TAB_SYM + a.n_sym + first;
       for (int i = 0; i < nr && prog < 0; i++) {
         const int pg = rtab[i];
@@ -938,10 +950,10 @@ __device__ __forceinline__ void round_execute(const RoundArgs &a, Lds &L, const 
             p.state[x] = (uint8_t)st;
           }
           if ((st & ST_ACTIVE) && !(st & ST_PEND)) {
+            // a queued node gets the full readiness test at once: it is
+            // mostly ready, and its memo would only add two dependent reads
             s = x;
-            // (learned mode: a kept node gets the full test, so that the
-            // predictor sees all of its arguments)
-            memo = (a.use_memo && R.mode != 2) ? (int)((st & ST_MEMO_MASK) >> ST_MEMO_SHIFT) : 0;
+            memo = (int)((st & ST_MEMO_MASK) >> ST_MEMO_SHIFT);
           }
         }
       }
@@ -1005,59 +1017,73 @@ __device__ __forceinline__ void round_execute(const RoundArgs &a, Lds &L, const 
                 pack4(vw.w >> sh) << 12;
         if (npt < 16) wmask &= (1 << npt) - 1;
       }
-      // classify the thread's slots; otherwise, for live slots with a memo,
-      // read the recorded argument of all of them first, then all their
-      // states, so the dependent loads of the 16 slots overlap
+      // candidate slots, found for the 16 bytes at once: a byte whose low 7
+      // bits are not all zero (live and not a plain normal form, or a
+      // marker), within 0 < slot < n
+      int cand = nz7x4((unsigned)sw[0]) | nz7x4((unsigned)sw[1]) << 4 |
+                 nz7x4((unsigned)sw[2]) << 8 | nz7x4((unsigned)sw[3]) << 12;
+      if (npt < 16) cand &= (1 << npt) - 1;
+      if (base == 0) cand &= ~1;
+      {
+        const int lim = n - base;
+        if (lim < npt) cand &= lim > 0 ? (1 << lim) - 1 : 0;
+      }
+      // live non-normal-form slots among them (markers of the previous round
+      // are retired on the way; a retired marker carries no memo), and those
+      // with a memo; off the wake path, the recorded arguments of all of
+      // them are read first, then all their states, so the loads overlap
       ivec16 cidx = (ivec16)(0);   // memo argument slot (0: none)
       int pending = 0;             // bit j: slot j is live and not in normal form
-#pragma unroll
-      for (int j = 0; j < 16; j++) {
-        if (j < npt) {
-          const int slot = base + j;
-          const unsigned byte = ((unsigned)sw[j >> 2] >> ((j & 3) * 8)) & 0xffu;
-          unsigned st = (slot < n && slot > 0) ? byte : 0u;
-          if ((st & 0x7fu) == 0) continue;  // free or plain normal form
-          if (st & ST_PEND) {
-            if (((st >> 2) & 1u) == e) continue;  // created this round
-            st = (st & ST_NF) ? ST_NF : ST_ACTIVE;
-            p.state[slot] = (uint8_t)st;
-            if (st == ST_NF) continue;
-          }
-          pending |= 1 << j;
-          const int memo = a.use_memo ? (int)((st & ST_MEMO_MASK) >> ST_MEMO_SHIFT) : 0;
-          if (memo && !wake_sweep) {
+      int memoed = 0;              // bit j: slot j is live and has a memo
+      for (int m = cand; m; m &= m - 1) {
+        const int j = __builtin_ctz(m);
+        const int slot = base + j;
+        unsigned st = ((unsigned)sw[j >> 2] >> ((j & 3) * 8)) & 0xffu;
+        if (st & ST_PEND) {
+          if (((st >> 2) & 1u) == e) continue;  // created this round
+          st = (st & ST_NF) ? ST_NF : ST_ACTIVE;
+          p.state[slot] = (uint8_t)st;
+          if (st != ST_NF) pending |= 1 << j;
+          continue;
+        }
+        pending |= 1 << j;
+        if (a.use_memo && (st & ST_MEMO_MASK)) {
+          memoed |= 1 << j;
+          if (!wake_sweep) {
+            const int memo = (int)((st & ST_MEMO_MASK) >> ST_MEMO_SHIFT);
             const int c = p.args[(int64_t)slot * A + (memo - 1)];
             cidx[j] = ((unsigned)c < (unsigned)p.N) ? c : 0;
           }
         }
       }
-      int cst[16];
-#pragma unroll
-      for (int j = 0; j < 16; j++) cst[j] = (pending >> j & 1) && cidx[j] ? p.state[cidx[j]] : 0;
       if (t == t_first) tmark(a, r, 13);
-      // the slots of this thread to examine
-      int exam = 0;
-#pragma unroll
-      for (int j = 0; j < 16; j++) {
-        if (j >= npt) break;
-        const bool live = pending >> j & 1;
-        const unsigned byte = ((unsigned)sw[j >> 2] >> ((j & 3) * 8)) & 0xffu;
-        const int memo = (!live || (byte & ST_PEND) || !a.use_memo)
-                             ? 0
-                             : (int)((byte & ST_MEMO_MASK) >> ST_MEMO_SHIFT);
-        const bool still = wake_sweep ? (memo && !((wmask >> j) & 1))
-                                      : (memo && cidx[j] && !nf_visible((unsigned)cst[j], e));
-        if (memo && !still && wake_sweep) {
-          // honour (clear) the wake bit of the previous rounds' parity; a bit
-          // set in this round stays for the next one
-          const int slot = base + j;
+      // sleeping slots that stay asleep: no wake bit of an earlier round
+      // (plain mode), or the memo argument still not a visible normal form
+      int still = 0;
+      if (wake_sweep) {
+        still = memoed & ~wmask;
+        // honour (clear) the wake bits of the previous rounds' parity that
+        // wake a slot; a bit set in this round stays for the next one
+        for (int m = memoed & wmask; m; m &= m - 1) {
+          const int slot = base + __builtin_ctz(m);
           atomicAnd(reinterpret_cast<unsigned *>(p.wake + (slot & ~3)),
                     ~((1u << (1u - e)) << (8 * (slot & 3))));
         }
-        C.active += live;
-        C.memo += still;  // still blocked by the same argument
-        if (live && !still) exam |= 1 << j;
+      } else if (memoed) {
+        ivec16 cst = (ivec16)(0);
+        for (int m = memoed; m; m &= m - 1) {
+          const int j = __builtin_ctz(m);
+          if (cidx[j]) cst[j] = p.state[cidx[j]];
+        }
+        for (int m = memoed; m; m &= m - 1) {
+          const int j = __builtin_ctz(m);
+          if (cidx[j] && !nf_visible((unsigned)cst[j], e)) still |= 1 << j;
+        }
       }
+      C.active += __popc(pending);
+      C.memo += __popc(still);  // still blocked by the same argument
+      // the slots of this thread to examine
+      const int exam = pending & ~still;
       // append them to the LDS work list: a wave prefix sum of the counts
       // and one LDS atomic per wave
       {
