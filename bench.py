@@ -177,6 +177,7 @@ def main():
     ap.add_argument("--persistent", action="store_true")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--npt", type=int, default=0)
+    ap.add_argument("--max-grid", type=int, default=0, help="workgroups per launch cap (0 = default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default (or given) block and nodes per thread")
@@ -205,7 +206,8 @@ def main():
     if args.mode == "learned" or "learned" in compare:
         ctx.set_predictor(load_predictor(w, args.weights))
     opts = T.Options(block=args.block, nodes_per_thread=args.npt, mode=MODES[args.mode],
-                     persistent=1 if args.persistent else 0, threshold=args.threshold)
+                     persistent=1 if args.persistent else 0, threshold=args.threshold,
+                     max_grid=args.max_grid)
     tune = None
     if not args.no_autotune and not args.block and not args.npt:
         # the launch shape is tuned on the parent-notification frontier (six

@@ -113,6 +113,10 @@ typedef struct {
                                 rounds, so that a node the predictor drops
                                 waits at most k rounds (0 = 8; -1 = only
                                 when the frontier is empty or a round stalls) */
+  int32_t max_grid;          /* most workgroups a round launch uses (0 = 8 per
+                                compute unit); larger grids keep more sweep
+                                tiles in flight, smaller ones fewer idle
+                                workgroups in frontier rounds */
 } trs_opts;
 
 typedef struct {

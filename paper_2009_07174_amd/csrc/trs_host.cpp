@@ -468,6 +468,7 @@ void trs_default_opts(trs_opts *o) {
   o->trace_cap = 0;
   o->label_horizon = 0;
   o->sweep_every = 0;
+  o->max_grid = 0;
 }
 
 trs_status trs_create(trs_ctx **out, const trs_config *cfg) {
@@ -680,6 +681,8 @@ trs_status trs_normalize(trs_ctx *c, const trs_opts *opts_in, trs_stats *stats) 
       return c->fail(TRS_E_ARG, "threshold must be in [0, 1]");
   }
   if (o.trace < 0 || o.trace > 65536) return c->fail(TRS_E_ARG, "trace rate must be 0..65536");
+  if (o.max_grid < 0 || o.max_grid > (1 << 20))
+    return c->fail(TRS_E_ARG, "max_grid must be 0..2^20");
   if (o.label_horizon < 0 || o.sweep_every < -1)
     return c->fail(TRS_E_ARG, "label_horizon must be >= 0, sweep_every >= -1");
   if (o.trace && o.mode != TRS_MODE_PLAIN)
@@ -836,12 +839,28 @@ trs_status trs_normalize(trs_ctx *c, const trs_opts *opts_in, trs_stats *stats) 
     HIPCHK(c, hipMemsetAsync(d_trace, 0, (size_t)trace_cap * TRACE_FIELDS * 8, s));
     ra.trace = d_trace;
     ra.trace_cap = trace_cap;
+    // TRS_PHASE_SHIFT=s samples rounds r with r mod 2^s < 2 over the whole run
+    if (const char *sh = std::getenv("TRS_PHASE_SHIFT")) ra.trace_shift = std::atoi(sh);
+  }
+  // opt-in per-workgroup timing of one round (TRS_WG_TRACE=round:path)
+  const char *wgt_env = std::getenv("TRS_WG_TRACE");
+  long long *d_wgt = nullptr;
+  std::string wgt_path;
+  if (wgt_env) {
+    const char *colon = std::strchr(wgt_env, ':');
+    if (colon) {
+      ra.wgtrace_round = std::atoi(wgt_env);
+      wgt_path = colon + 1;
+      HIPCHK(c, hipMalloc(&d_wgt, 4096 * 8 * 8));
+      HIPCHK(c, hipMemsetAsync(d_wgt, 0, 4096 * 8 * 8, s));
+      ra.wgtrace = d_wgt;
+    }
   }
   const size_t lds = trs_round_lds_bytes(B, npt, ra.tab_words, c->n_rules);
   if (lds > 160 * 1024) return c->fail(TRS_E_ARG, "configuration needs too much LDS");
   const int TILE = B * npt;
   HIPCHK(c, trs_prepare_kernels(A, lds));
-  int gmax = 8 * c->cu_count;
+  int gmax = o.max_grid > 0 ? o.max_grid : 8 * c->cu_count;
   if (o.persistent) {
     gmax = trs_max_resident(A, B, lds, c->cfg.device);
     if (gmax <= 0) return c->fail(TRS_E_HIP, "persistent kernel cannot be resident");
@@ -952,6 +971,20 @@ trs_status trs_normalize(trs_ctx *c, const trs_opts *opts_in, trs_stats *stats) 
   HIPCHK(c, hipStreamSynchronize(s));
   float ms = 0.f;
   HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+  if (d_wgt) {
+    std::vector<long long> t(4096 * 8);
+    HIPCHK(c, hipMemcpy(t.data(), d_wgt, t.size() * 8, hipMemcpyDeviceToHost));
+    (void)hipFree(d_wgt);
+    if (FILE *f = std::fopen(wgt_path.c_str(), "w")) {
+      for (int i = 0; i < 4096; i++) {
+        if (!t[i * 8]) continue;
+        std::fprintf(f, "%d", i);
+        for (int j = 0; j < 8; j++) std::fprintf(f, " %lld", t[i * 8 + j]);
+        std::fprintf(f, "\n");
+      }
+      std::fclose(f);
+    }
+  }
   if (d_trace) {
     std::vector<long long> t((size_t)trace_cap * TRACE_FIELDS);
     HIPCHK(c, hipMemcpy(t.data(), d_trace, t.size() * 8, hipMemcpyDeviceToHost));

@@ -30,7 +30,12 @@ struct RoundArgs {
   int32_t *trace_n;     // records logged so far
   unsigned long long *bar;  // grid barrier counter (persistent kernel)
   long long *trace;     // optional phase timestamps of workgroup 0 (null: off)
-  int32_t trace_cap;    // rounds the trace holds (TRACE_FIELDS words each)
+  int32_t trace_cap;    // rows the trace holds (TRACE_FIELDS words each)
+  int32_t trace_shift;  // 0: row r is round r; s > 0: rounds r with
+                        // r mod 2^s < 2, in row 2 (r >> s) + (r & 1)
+  long long *wgtrace;   // optional per-workgroup timing of round wgtrace_round:
+                        // 8 words per workgroup (null: off)
+  int32_t wgtrace_round;
 };
 
 // Phase timestamps (clock64) recorded by thread 0 of workgroup 0 per round:

@@ -60,6 +60,13 @@ __device__ __forceinline__ int ld(const int32_t *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Store of a control word that another workgroup of the same launch reads
+// (with ld): an agent-scope store is coherent with agent-scope loads and
+// fetch-adds on every XCD, where a plain store could stay in this XCD's L2.
+__device__ __forceinline__ void st(int32_t *p, int v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // 32-bit integer hash (multiply / xor-shift), used to sample trace records
 __device__ __forceinline__ uint32_t mix32(uint32_t x) {
   x ^= x >> 16;
@@ -219,9 +226,20 @@ __device__ __forceinline__ int xcd_remap(int wg, int G) {
 }
 
 // phase timestamp (thread 0 of workgroup 0, when tracing is on)
+__device__ __forceinline__ void tmark_any(const RoundArgs &a, int r, int field) {
+  if (!a.trace) return;
+  int row = r;
+  if (a.trace_shift > 0) {
+    if ((r & ((1 << a.trace_shift) - 1)) >= 2) return;
+    row = 2 * (r >> a.trace_shift) + (r & 1);
+  }
+  if (row < a.trace_cap) a.trace[(size_t)row * TRACE_FIELDS + field] = (long long)wall_clock64();
+}
+
+// Phase timestamp (100 MHz wall clock, comparable across compute units) of
+// workgroup 0's work on round r.
 __device__ __forceinline__ void tmark(const RoundArgs &a, int r, int field) {
-  if (a.trace && blockIdx.x == 0 && threadIdx.x == 0 && r < a.trace_cap)
-    a.trace[(size_t)r * TRACE_FIELDS + field] = clock64();
+  if (a.trace && blockIdx.x == 0 && threadIdx.x == 0) tmark_any(a, r, field);
 }
 
 struct Counters {
@@ -275,6 +293,15 @@ __device__ __forceinline__ void notify_parent(const RoundArgs &a, const Lds &L, 
 }
 
 typedef __attribute__((address_space(3))) void lds_void;
+
+// This wave's prefetch entries (state: which = 0, wake: which = 1), from
+// wave-uniform values only, so that the address stays in scalar registers
+// (a spilled vector address would be reloaded, and the wait for that reload
+// would also wait for the prefetch just issued).
+__device__ __forceinline__ uint4 *pf_wave(const Lds &L, int which) {
+  const int w0 = __builtin_amdgcn_readfirstlane((int)threadIdx.x & ~63);
+  return L.pf + which * (int)blockDim.x + w0;
+}
 
 // Asynchronous copy of 16 bytes per lane from global memory straight into
 // LDS (no registers held while in flight): lane l of the wave writes
@@ -361,7 +388,7 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
     for (int j = 0; j < A; j++) raw[j] = p.args[(int64_t)s * A + j];
     {
       if ((unsigned)f >= (unsigned)a.n_sym) {
-        cnt->err = -9;
+        st(&cnt->err, -9);
       } else {
         info = tab[TAB_SYM + f];
         ar = info & 0xff;
@@ -375,7 +402,7 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
           }
         }
         if (!ok) {
-          cnt->err = -9;
+          st(&cnt->err, -9);
         } else {
           int bits = 0;
 #pragma unroll
@@ -469,7 +496,7 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
           } else {
             c = p.args[(int64_t)ps[par] * A + pos];
             if ((unsigned)c >= (unsigned)N || c == 0) {  // broken invariant: stop safely
-              cnt->err = -9;
+              st(&cnt->err, -9);
               c = ps[par];
               ok = false;
             }
@@ -493,7 +520,7 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
     if ((int64_t)fsQ + base.y < N)
       SQ[fsQ + base.y] = free_slot;
     else
-      cnt->err = -9;
+      st(&cnt->err, -9);
   }
   ivec8 ns = (ivec8)(0);  // slots of the new nodes
   bool okalloc = true;
@@ -508,7 +535,7 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
     }
   }
   if (prog >= 0 && !okalloc) {
-    cnt->err = -5;  // TRS_E_POOL
+    st(&cnt->err, -5);  // TRS_E_POOL
     prog = -1;
   }
   const uint8_t pend_nf = (uint8_t)(ST_NF | ST_PEND | (e << 2));
@@ -571,7 +598,7 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
       const int src = ps[rootpat];
       int sh = p.hss[src];
       if ((unsigned)sh >= (unsigned)a.n_sym) {
-        cnt->err = -9;
+        st(&cnt->err, -9);
         sh = 0;
       }
       const int sar = tab[TAB_SYM + sh] & 0xff;
@@ -584,7 +611,7 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
             atomicAdd(&p.rc[cj], 1);
             C.rcops++;
           } else {
-            cnt->err = -9;
+            st(&cnt->err, -9);
           }
         }
       }
@@ -682,7 +709,7 @@ __device__ __forceinline__ int collect(const RoundArgs &a, const Lds &L, RoundCn
                                        Counters &C) {
   const Pool &p = a.p;
   if ((unsigned)d >= (unsigned)p.N || d == 0) {
-    cnt->err = -9;
+    st(&cnt->err, -9);
     return 0;
   }
   const int f = p.hss[d];
@@ -692,7 +719,7 @@ __device__ __forceinline__ int collect(const RoundArgs &a, const Lds &L, RoundCn
     if (j < ar) {
       const int c = p.args[(int64_t)d * A + j];
       if ((unsigned)c >= (unsigned)p.N || c == 0) {
-        cnt->err = -9;
+        st(&cnt->err, -9);
         continue;
       }
       const int old = atomicSub(&p.rc[c], 1);
@@ -889,14 +916,17 @@ __device__ __forceinline__ void round_execute(const RoundArgs &a, Lds &L, const 
   const int nlist = rs.nlist, ntiles = rs.ntiles, need = rs.need;
   const int G = gridDim.x;
   tmark(a, r, 1);
+  if (a.wgtrace && r == a.wgtrace_round && tid == 0 && wg < 4096)
+    a.wgtrace[wg * 8 + 4] = (long long)wall_clock64();
   if (wg == 0 && tid == 0) {
-    ctl->n[r3] = n;
-    ctl->fs[r3][0] = fs0;
-    ctl->fs[r3][1] = fs1;
+    st(&ctl->n[r3], n);
+    st(&ctl->fs[r3][0], fs0);
+    st(&ctl->fs[r3][1], fs1);
     RoundCnt *nx = &ctl->cnt[(r + 1) % 3];
-    nx->alloc = nx->push = nx->dead = nx->active = nx->err = nx->front = nx->ret = nx->full = 0;
-    nx->prog = 0;
-    ctl->cnt[r3].full = (full || quiescent) ? 1 : 0;
+    for (int32_t *w : {&nx->alloc, &nx->push, &nx->dead, &nx->active, &nx->err, &nx->front,
+                       &nx->ret, &nx->full, &nx->prog})
+      st(w, 0);
+    st(&ctl->cnt[r3].full, (full || quiescent) ? 1 : 0);
     if ((unsigned long long)n > L.lstat[LSTAT_PEAK]) L.lstat[LSTAT_PEAK] = n;
     if (nd > 0) L.lstat[LSTAT_GC]++;
     if (full) L.lstat[LSTAT_FULL]++;
@@ -962,6 +992,12 @@ __device__ __forceinline__ void round_execute(const RoundArgs &a, Lds &L, const 
   }
 
   tmark(a, r, 3);
+  const bool wgt = a.wgtrace && r == a.wgtrace_round && tid == 0 && wg < 4096;
+  if (wgt) {
+    a.wgtrace[wg * 8 + 0] = (long long)wall_clock64();
+    a.wgtrace[wg * 8 + 6] = __smid();
+  }
+  int ntile_done = 0, nitems = 0;
   // ---- 2./3. full sweep of all slots below n, rewrite of the ready ones
   if (full) {
     const int npt = a.npt;
@@ -978,8 +1014,8 @@ __device__ __forceinline__ void round_execute(const RoundArgs &a, Lds &L, const 
     const int t_first = t;
     if (ahead && t < ntiles) {
       const int64_t b0 = (int64_t)t * TILE + tid * 16;
-      lds_fetch16(p.state + b0, L.pf + (tid & ~63));  // this wave's entries
-      if (wake_sweep) lds_fetch16(p.wake + b0, L.pf + B + (tid & ~63));
+      lds_fetch16(p.state + b0, pf_wave(L, 0));
+      if (wake_sweep) lds_fetch16(p.wake + b0, pf_wave(L, 1));
     }
     for (; t < ntiles; t += Ga) {
       const int base = t * TILE + tid * npt;
@@ -992,8 +1028,8 @@ __device__ __forceinline__ void round_execute(const RoundArgs &a, Lds &L, const 
         asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
         if (t + Ga < ntiles) {
           const int64_t nb = (int64_t)(t + Ga) * TILE + tid * 16;
-          lds_fetch16(p.state + nb, L.pf + (tid & ~63));
-          if (wake_sweep) lds_fetch16(p.wake + nb, L.pf + B + (tid & ~63));
+          lds_fetch16(p.state + nb, pf_wave(L, 0));
+          if (wake_sweep) lds_fetch16(p.wake + nb, pf_wave(L, 1));
         }
       } else {
         vs = load_bytes(p.state + base, npt);
@@ -1120,10 +1156,17 @@ __device__ __forceinline__ void round_execute(const RoundArgs &a, Lds &L, const 
         W -= take;
       }
       if (t == t_first) tmark(a, r, 15);
+      ntile_done++;
+      nitems += exam ? __popc(exam) : 0;
     }
   }
 
   tmark(a, r, 4);
+  if (wgt) {
+    a.wgtrace[wg * 8 + 1] = (long long)wall_clock64();
+    a.wgtrace[wg * 8 + 2] = ntile_done;
+    a.wgtrace[wg * 8 + 3] = nitems;
+  }
   // ---- per-workgroup statistics: wave sums, added by one lane per wave to
   // the workgroup's LDS totals; only the liveness flag of the round goes to
   // global memory
@@ -1152,15 +1195,17 @@ __device__ __forceinline__ void round_execute(const RoundArgs &a, Lds &L, const 
   }
   __syncthreads();
   if (tid == 0 && L.misc[32]) {
-    cnt->active = 1;
+    st(&cnt->active, 1);
     L.misc[32] = 0;
   }
   if (tid == 0 && L.misc[33]) {
-    cnt->prog = 1;
+    st(&cnt->prog, 1);
     L.misc[33] = 0;
   }
   __syncthreads();
   tmark(a, r, 5);
+  if (a.wgtrace && r == a.wgtrace_round && tid == 0 && wg < 4096)
+    a.wgtrace[wg * 8 + 5] = (long long)wall_clock64();
 }
 
 // Add this workgroup's statistics of the launch to the control block (once,
@@ -1269,9 +1314,16 @@ __global__ void __launch_bounds__(1024) k_round(RoundArgs a) {
       __hip_atomic_store(&ctl->r_reached, rs.stop || rs.need == 1 ? rs.r + 1 : rs.r,
                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
+  // Every wave waits for its own memory operations of the launch (the round
+  // counters' fetch-adds among them) to complete before the workgroup takes
+  // its ticket, so the workgroup that draws the last ticket sees every
+  // count.  Nothing else of this launch is read by another workgroup before
+  // the launch ends, so no agent-scope fence is needed here: on gfx950 that
+  // fence writes back and invalidates the whole L2 of the XCD, and taken by
+  // each of thousands of workgroups per round it cost more than the sweep.
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (tid == 0) {
-    __threadfence();
     const int t = atomicAdd(&ctl->ticket, 1);
     if (t == min(need0, (int)gridDim.x) - 1) {
       // last working workgroup of the launch: every round it covered is
@@ -1280,6 +1332,7 @@ __global__ void __launch_bounds__(1024) k_round(RoundArgs a) {
       const int rr = max(ld(&ctl->r_cur) + 1, ld(&ctl->r_reached));
       const RoundState nx = round_state(a, rr);
       publish(ctl, nx);
+      tmark_any(a, rr - 1, 11);
       __hip_atomic_store(&ctl->next_need, nx.need, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_store(&ctl->ticket, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_store(&ctl->r_cur, rr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

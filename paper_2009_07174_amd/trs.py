@@ -39,7 +39,7 @@ class trs_opts(ctypes.Structure):
                 ("max_rounds", ctypes.c_int64), ("threshold", ctypes.c_float),
                 ("persistent", ctypes.c_int32), ("trace", ctypes.c_int32),
                 ("trace_cap", ctypes.c_int64), ("label_horizon", ctypes.c_int32),
-                ("sweep_every", ctypes.c_int32)]
+                ("sweep_every", ctypes.c_int32), ("max_grid", ctypes.c_int32)]
 
 
 class trs_stats(ctypes.Structure):
@@ -355,12 +355,13 @@ class Options:
     trace_cap: int = 0
     label_horizon: int = 0
     sweep_every: int = 0
+    max_grid: int = 0
 
     def to_c(self) -> trs_opts:
         o = trs_default_opts()
         for k in ("mode", "block", "nodes_per_thread", "rounds_per_poll", "max_rounds",
                   "threshold", "persistent", "trace", "trace_cap", "label_horizon",
-                  "sweep_every"):
+                  "sweep_every", "max_grid"):
             setattr(o, k, getattr(self, k))
         return o
 
