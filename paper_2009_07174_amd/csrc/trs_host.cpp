@@ -567,7 +567,18 @@ trs_status trs_load_rules(trs_ctx *c, int32_t n_sym, const int32_t *arity, int32
   for (int f = 0; f < n_sym; f++) {
     if (by_sym[f].size() > 255)
       return c->fail(TRS_E_LIMIT, "more than 255 rules for one symbol");
-    tab[TAB_SYM + f] = tab_sym_word(ar[f], (int)by_sym[f].size(), first);
+    // argument positions whose own entries some rule of f reads: a pattern
+    // deeper than the argument's symbol, or a right-hand side that is the
+    // variable bound to the argument (the root takes over its entries)
+    int deep = 0;
+    for (int r : by_sym[f]) {
+      for (const PNode &q : lhs[r])
+        if (q.parent > 0 && lhs[r][q.parent].parent == 0) deep |= 1 << lhs[r][q.parent].pos;
+      if (rhs[r][0].var >= 0)
+        for (const PNode &q : lhs[r])
+          if (q.var == rhs[r][0].var && q.parent == 0) deep |= 1 << q.pos;
+    }
+    tab[TAB_SYM + f] = tab_sym_word(ar[f], (int)by_sym[f].size(), first, deep);
     for (int r : by_sym[f]) order.push_back(r);
     first += (int)by_sym[f].size();
   }
@@ -834,13 +845,18 @@ trs_status trs_normalize(trs_ctx *c, const trs_opts *opts_in, trs_stats *stats) 
   const char *trace_path = std::getenv("TRS_PHASE_TRACE");
   long long *d_trace = nullptr;
   const int trace_cap = 4096;
+  // TRS_PHASE_MAX set: a row per traced round and workgroup (the first 64)
+  const bool trace_wg = trace_path && std::getenv("TRS_PHASE_MAX") != nullptr;
+  const size_t trace_rows = (size_t)trace_cap * (trace_wg ? 64 : 1);
+  const size_t trace_bytes = trace_rows * TRACE_FIELDS * 8;
   if (trace_path) {
-    HIPCHK(c, hipMalloc(&d_trace, (size_t)trace_cap * TRACE_FIELDS * 8));
-    HIPCHK(c, hipMemsetAsync(d_trace, 0, (size_t)trace_cap * TRACE_FIELDS * 8, s));
+    HIPCHK(c, hipMalloc(&d_trace, trace_bytes));
+    HIPCHK(c, hipMemsetAsync(d_trace, 0, trace_bytes, s));
     ra.trace = d_trace;
     ra.trace_cap = trace_cap;
     // TRS_PHASE_SHIFT=s samples rounds r with r mod 2^s < 2 over the whole run
     if (const char *sh = std::getenv("TRS_PHASE_SHIFT")) ra.trace_shift = std::atoi(sh);
+    ra.trace_max = trace_wg;
   }
   // opt-in per-workgroup timing of one round (TRS_WG_TRACE=round:path)
   const char *wgt_env = std::getenv("TRS_WG_TRACE");
@@ -986,13 +1002,23 @@ trs_status trs_normalize(trs_ctx *c, const trs_opts *opts_in, trs_stats *stats) 
     }
   }
   if (d_trace) {
-    std::vector<long long> t((size_t)trace_cap * TRACE_FIELDS);
+    std::vector<long long> t(trace_rows * TRACE_FIELDS);
     HIPCHK(c, hipMemcpy(t.data(), d_trace, t.size() * 8, hipMemcpyDeviceToHost));
     (void)hipFree(d_trace);
+    // one line per round (workgroup 0), or per round and workgroup ("row wg
+    // fields", rows with a timestamp only)
     if (FILE *f = std::fopen(trace_path, "w")) {
-      for (int i = 0; i < trace_cap; i++) {
-        std::fprintf(f, "%d", i);
-        for (int j = 0; j < TRACE_FIELDS; j++) std::fprintf(f, " %lld", t[(size_t)i * TRACE_FIELDS + j]);
+      for (size_t i = 0; i < trace_rows; i++) {
+        const long long *v = &t[i * TRACE_FIELDS];
+        if (trace_wg) {
+          bool any = false;
+          for (int j = 0; j < TRACE_FIELDS; j++) any |= v[j] != 0;
+          if (!any) continue;
+          std::fprintf(f, "%zu %zu", i / 64, i % 64);
+        } else {
+          std::fprintf(f, "%zu", i);
+        }
+        for (int j = 0; j < TRACE_FIELDS; j++) std::fprintf(f, " %lld", v[j]);
         std::fprintf(f, "\n");
       }
       std::fclose(f);

@@ -33,6 +33,8 @@ struct RoundArgs {
   int32_t trace_cap;    // rows the trace holds (TRACE_FIELDS words each)
   int32_t trace_shift;  // 0: row r is round r; s > 0: rounds r with
                         // r mod 2^s < 2, in row 2 (r >> s) + (r & 1)
+  int32_t trace_max;    // nonzero: fields from 2 on hold the latest time any
+                        // workgroup passed the point (else workgroup 0's)
   long long *wgtrace;   // optional per-workgroup timing of round wgtrace_round:
                         // 8 words per workgroup (null: off)
   int32_t wgtrace_round;

@@ -45,6 +45,8 @@
 // persistent form needs a single device-wide barrier per round.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "trs_kernels.h"
 
 #define MAXPAT 8
@@ -65,6 +67,18 @@ __device__ __forceinline__ int ld(const int32_t *p) {
 // fetch-adds on every XCD, where a plain store could stay in this XCD's L2.
 __device__ __forceinline__ void st(int32_t *p, int v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Workgroup barrier for LDS traffic only: each wave waits for its own LDS
+// operations, not for its global stores and atomics.  Within a round no wave
+// reads what another wave of its workgroup wrote to global memory (the
+// method tolerates either value there, as it must for other workgroups), so
+// the barriers inside a round need not wait for write acknowledgements; the
+// full barrier (__syncthreads) is kept where a round ends.
+__device__ __forceinline__ void lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 // 32-bit integer hash (multiply / xor-shift), used to sample trace records
@@ -111,6 +125,18 @@ __device__ __forceinline__ int wave_incl_scan(int x) {
 typedef int ivec4 __attribute__((ext_vector_type(4)));
 typedef int ivec8 __attribute__((ext_vector_type(8)));
 typedef int ivec16 __attribute__((ext_vector_type(16)));
+typedef int ivec32 __attribute__((ext_vector_type(32)));
+
+// Per-argument values of a node (A entries), and the argument entries of its
+// arguments (A x A), each one register vector of the smallest fitting size
+// (they are indexed at run time, so the whole vector stays in registers).
+template <int A>
+using VecA = typename std::conditional<(A <= 4), ivec4, ivec8>::type;
+template <int A>
+using GcVec = typename std::conditional<
+    (A * A <= 4), ivec4,
+    typename std::conditional<(A * A <= 8), ivec8,
+                              typename std::conditional<(A * A <= 16), ivec16, ivec32>::type>::type>::type;
 
 // An LDS-buffered append list: lanes append with an LDS atomic, the
 // workgroup flushes the buffer to the global list with one atomic.
@@ -136,6 +162,9 @@ struct Lds {
   // flushed once at the end of the launch: STAT_* then gc rounds, full
   // sweeps, peak extent
   unsigned long long *lstat;
+  // phase timestamps of this workgroup's current round (per-workgroup phase
+  // trace only), written to the trace buffer when the round ends
+  unsigned long long *tstamp;
   Queue qd, qf, qr;  // dead, frontier, retire
 };
 
@@ -169,7 +198,7 @@ __device__ __forceinline__ void qcopy(const Lds &L, const Queue &q, int k, int64
 
 // Flush the three LDS queues (whole workgroup).
 __device__ __forceinline__ void qflush(const Lds &L, int64_t cap) {
-  __syncthreads();
+  lds_sync();
   // (each queue is named statically: selecting one at run time would force
   // the workgroup's LDS descriptors into scratch memory)
   if (threadIdx.x == 0)
@@ -178,13 +207,13 @@ __device__ __forceinline__ void qflush(const Lds &L, int64_t cap) {
     qreserve(L, L.qf, 1);
   else if (threadIdx.x == 2)
     qreserve(L, L.qr, 2);
-  __syncthreads();
+  lds_sync();
   qcopy(L, L.qd, 0, cap);
   qcopy(L, L.qf, 1, cap);
   qcopy(L, L.qr, 2, cap);
-  __syncthreads();
+  lds_sync();
   if (threadIdx.x < 3) L.misc[1 + threadIdx.x] = 0;
-  __syncthreads();
+  lds_sync();
 }
 
 // Workgroup-wide reservation of m1 items on counter c1 and m2 items on c2.
@@ -197,7 +226,7 @@ __device__ __forceinline__ int2 wg_reserve2(const Lds &L, int m1, int32_t *c1, i
     L.misc[8 + w] = i1;
     L.misc[47 + w] = i2;
   }
-  __syncthreads();
+  lds_sync();
   if (threadIdx.x == 0) {
     int r1 = 0, r2 = 0;
     for (int i = 0; i < nw; i++) {
@@ -210,11 +239,11 @@ __device__ __forceinline__ int2 wg_reserve2(const Lds &L, int m1, int32_t *c1, i
     L.misc[4] = r1 ? atomicAdd(c1, r1) : 0;
     L.misc[5] = r2 ? atomicAdd(c2, r2) : 0;
   }
-  __syncthreads();
+  lds_sync();
   int2 b;
   b.x = L.misc[4] + L.misc[8 + w] + i1 - m1;
   b.y = L.misc[5] + L.misc[47 + w] + i2 - m2;
-  __syncthreads();  // misc reused by the next call
+  lds_sync();  // misc reused by the next call
   return b;
 }
 
@@ -226,20 +255,51 @@ __device__ __forceinline__ int xcd_remap(int wg, int G) {
 }
 
 // phase timestamp (thread 0 of workgroup 0, when tracing is on)
-__device__ __forceinline__ void tmark_any(const RoundArgs &a, int r, int field) {
+__device__ __forceinline__ void tmark_any(const RoundArgs &a, int r, int field,
+                                          bool latest = false) {
   if (!a.trace) return;
   int row = r;
   if (a.trace_shift > 0) {
     if ((r & ((1 << a.trace_shift) - 1)) >= 2) return;
     row = 2 * (r >> a.trace_shift) + (r & 1);
   }
-  if (row < a.trace_cap) a.trace[(size_t)row * TRACE_FIELDS + field] = (long long)wall_clock64();
+  if (row >= a.trace_cap) return;
+  long long *w = a.trace + (size_t)row * TRACE_FIELDS + field;
+  const long long now = (long long)wall_clock64();
+  if (latest)
+    atomicMax(reinterpret_cast<unsigned long long *>(w), (unsigned long long)now);
+  else
+    *w = now;
 }
 
 // Phase timestamp (100 MHz wall clock, comparable across compute units) of
-// workgroup 0's work on round r.
-__device__ __forceinline__ void tmark(const RoundArgs &a, int r, int field) {
-  if (a.trace && blockIdx.x == 0 && threadIdx.x == 0) tmark_any(a, r, field);
+// round r: workgroup 0's, or with trace_max every workgroup's, kept in LDS
+// until the round ends (tflush), so that tracing adds no global write (and
+// no wait for one) inside the round.
+__device__ __forceinline__ void tmark(const RoundArgs &a, const Lds &L, int r, int field) {
+  if (!a.trace || threadIdx.x != 0) return;
+  if (a.trace_max)
+    L.tstamp[field] = wall_clock64();
+  else if (blockIdx.x == 0)
+    tmark_any(a, r, field);
+}
+
+// End of round r (per-workgroup trace): this workgroup's timestamps go to
+// row (sampled round, workgroup), for the first 64 workgroups.
+__device__ __forceinline__ void tflush(const RoundArgs &a, const Lds &L, int r) {
+  if (!a.trace || !a.trace_max || threadIdx.x != 0) return;
+  int row = r;
+  bool keep = true;
+  if (a.trace_shift > 0) {
+    keep = (r & ((1 << a.trace_shift) - 1)) < 2;
+    row = 2 * (r >> a.trace_shift) + (r & 1);
+  }
+  if (keep && row < a.trace_cap && blockIdx.x < 64) {
+    long long *w = a.trace + ((size_t)row * 64 + blockIdx.x) * TRACE_FIELDS;
+    for (int f = 0; f < TRACE_FIELDS; f++)
+      if (L.tstamp[f]) w[f] = (long long)L.tstamp[f];
+  }
+  for (int f = 0; f < TRACE_FIELDS; f++) L.tstamp[f] = 0;
 }
 
 struct Counters {
@@ -284,12 +344,12 @@ struct RoundCtx {
 };
 
 // Notify the parent of a node that just became a normal form (frontier modes).
-__device__ __forceinline__ void notify_parent(const RoundArgs &a, const Lds &L, const RoundCtx &R,
-                                              int s) {
-  const int par = a.p.par[s];
-  if (par > 0 && par < a.p.N) {
-    if (atomicExch(&a.p.qstamp[par], R.stamp) != R.stamp) qpush(L, L.qf, par, a.p.N);
-  }
+// Returns the parent to queue once the exchange's result is in (0: none); the
+// caller consumes it after issuing its other atomics, so their latencies
+// overlap.
+__device__ __forceinline__ int notify_parent(const RoundArgs &a, const RoundCtx &R, int par) {
+  if (par > 0 && par < a.p.N) return atomicExch(&a.p.qstamp[par], R.stamp) != R.stamp ? par : 0;
+  return 0;
 }
 
 typedef __attribute__((address_space(3))) void lds_void;
@@ -359,10 +419,19 @@ __device__ __forceinline__ void wake_parent(const RoundArgs &a, const RoundCtx &
 // called by every thread of the workgroup (contains the allocation barrier);
 // free_slot > 0: this lane also pushes that slot (a node collected in the
 // same pass) on the free stack SQ.
+// A slot's symbol, argument entries and parent hint, when the caller read
+// them together with the slot's state.
+template <int A>
+struct Pre {
+  bool have;
+  int f, par;
+  VecA<A> raw;
+};
+
 template <int A>
 __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, const RoundCtx &R,
                                              int s, int memo, bool memo_checked, int free_slot,
-                                             int32_t *SQ, int fsQ, Counters &C) {
+                                             int32_t *SQ, int fsQ, Counters &C, const Pre<A> &pre) {
   const Pool &p = a.p;
   const int32_t *tab = L.tab;
   const unsigned e = R.e;
@@ -372,8 +441,13 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
   RoundCnt *cnt = R.cnt;
   bool have = s > 0;
   int info = 0, ar = 0, f = 0;
-  ivec8 av = (ivec8)(0);
-  ivec8 ch = (ivec8)(-1);  // argument symbols (read with the argument states)
+  VecA<A> av = (VecA<A>)(0);
+  VecA<A> ch = (VecA<A>)(-1);  // argument symbols (read with the argument states)
+  // argument entries of the arguments at the positions where some rule of
+  // the symbol has a pattern below the argument (read with the argument
+  // states, so that matching such patterns needs no further read)
+  GcVec<A> gc = (GcVec<A>)(0);
+  int par_s = 0;  // parent hint (frontier mode), read with the slot's entries
   bool ready = false;
   int nfb = -1;  // >= 0: the slot was examined and is blocked; bit j set when
                  // argument j is a visible normal form or j >= arity
@@ -382,16 +456,23 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
     // the symbol and all A argument entries are read together (entries past
     // the arity lie within the slot's stride and are ignored), then the
     // states and symbols of the arguments together: two dependent levels
-    f = p.hss[s];
-    ivec8 raw = (ivec8)(0);
+    VecA<A> raw = (VecA<A>)(0);
+    if (pre.have) {
+      f = pre.f;
+      raw = pre.raw;
+      par_s = pre.par;
+    } else {
+      f = p.hss[s];
 #pragma unroll
-    for (int j = 0; j < A; j++) raw[j] = p.args[(int64_t)s * A + j];
+      for (int j = 0; j < A; j++) raw[j] = p.args[(int64_t)s * A + j];
+      if (R.mode == 1) par_s = p.par[s];
+    }
     {
       if ((unsigned)f >= (unsigned)a.n_sym) {
         st(&cnt->err, -9);
       } else {
         info = tab[TAB_SYM + f];
-        ar = info & 0xff;
+        ar = SYM_ARITY(info);
         bool ok = true;
 #pragma unroll
         for (int j = 0; j < A; j++) {
@@ -405,6 +486,8 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
           st(&cnt->err, -9);
         } else {
           int bits = 0;
+          // (not kept for arity 5: 25 more registers would spill)
+          const int deep = A <= 4 ? SYM_DEEP(info) : 0;
 #pragma unroll
           for (int j = 0; j < 5; j++) {
             if (j >= ar) {
@@ -412,6 +495,10 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
             } else if (j < A) {
               const unsigned st = p.state[av[j]];
               ch[j] = p.hss[av[j]];
+              if ((deep >> j) & 1) {
+#pragma unroll
+                for (int i = 0; i < A; i++) gc[j * A + i] = p.args[(int64_t)av[j] * A + i];
+              }
               if (nf_visible(st, e)) bits |= 1 << j;
             }
           }
@@ -469,11 +556,16 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
     if (rr >= 0 && rr < R.r && R.r - rr <= a.label_h && idx >= 0 && idx < a.trace_cap_rec)
       a.trace_rec[idx] |= 1ull << 32;
   }
-  tmark(a, R.r, 6);
+  tmark(a, L, R.r, 6);
   int prog = -1;
   bool nfset = false;
-  ivec16 ps = (ivec16)(0);  // ps[k]: slot matched by pattern node k (0 = the redex)
-  ps[0] = s;
+  // 3 bits per pattern node of the rule being matched (after matching: of the
+  // matched rule): 1 + the argument position of a node directly below the
+  // root, 0 for deeper nodes
+  unsigned d1 = 0;
+  // slot matched by pattern node k: the redex s for k = 0, else ps[k - 1]
+  ivec8 ps = (ivec8)(0);
+  auto pslot = [&](int k) { return k == 0 ? s : ps[k - 1]; };
   if (ready) {
     C.ready++;
     const int nr = (info >> 8) & 0xff, first = info >> 16;
@@ -485,6 +577,7 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
         const int pg = rtab[i];
         const int npat = tab[pg] & 15;
         bool ok = true;
+        d1 = 0;
         for (int k = 1; k <= npat && ok; k++) {
           const int pe = tab[pg + 5 + k];
           const int par = pe & 15, pos = (pe >> 4) & 15;
@@ -493,16 +586,18 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
           if (par == 0) {
             c = av[pos];
             if (!isvar) h = ch[pos];
+            if (A <= 4) d1 |= (unsigned)(pos + 1) << (3 * k);  // (gc is kept for A <= 4)
           } else {
-            c = p.args[(int64_t)ps[par] * A + pos];
+            const int jp = (int)((d1 >> (3 * par)) & 7);
+            c = jp ? gc[(jp - 1) * A + pos] : p.args[(int64_t)pslot(par) * A + pos];
             if ((unsigned)c >= (unsigned)N || c == 0) {  // broken invariant: stop safely
               st(&cnt->err, -9);
-              c = ps[par];
+              c = pslot(par);
               ok = false;
             }
             if (!isvar && ok) h = p.hss[c];
           }
-          ps[k] = c;
+          ps[k - 1] = c;
           if (!isvar && h != (pe >> 16)) ok = false;
         }
         if (ok) prog = pg;
@@ -513,9 +608,9 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
   const int hdr = prog >= 0 ? tab[prog] : 0;
   const int m = (hdr >> 4) & 15;
   C.alloc += m;
-  tmark(a, R.r, 7);
+  tmark(a, L, R.r, 7);
   const int2 base = wg_reserve2(L, m, &cnt->alloc, free_slot > 0 ? 1 : 0, &cnt->push);
-  tmark(a, R.r, 8);
+  tmark(a, L, R.r, 8);
   if (free_slot > 0) {
     if ((int64_t)fsQ + base.y < N)
       SQ[fsQ + base.y] = free_slot;
@@ -539,10 +634,11 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
     prog = -1;
   }
   const uint8_t pend_nf = (uint8_t)(ST_NF | ST_PEND | (e << 2));
+  int note = 0;  // parent to queue (frontier mode), once its exchange returns
   if (prog >= 0) {
     C.fired++;
     const int rsym = tab[prog + 1];
-    const int ro = tab[prog + 2], no = tab[prog + 3], dl = tab[prog + 4], rid = tab[prog + 5];
+    const int ro = tab[prog + 2], no = tab[prog + 3], dl = tab[prog + 4];
     const bool var_root = (hdr >> 8) & 1, root_nf = (hdr >> 9) & 1, root_ready = (hdr >> 10) & 1;
     const int npos = (hdr >> 12) & 15, nneg = (hdr >> 16) & 15, rootpat = (hdr >> 20) & 15;
     // new nodes, children before parents
@@ -552,13 +648,13 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
       const int h = tab[q];
       const int sym = h & 0xffff, rci = (h >> 16) & 0x3f, bnf = (h >> 22) & 1;
       const int nready = (h >> 23) & 1, refr = (h >> 24) & 15;
-      const int ar2 = tab[TAB_SYM + sym] & 0xff;
+      const int ar2 = SYM_ARITY(tab[TAB_SYM + sym]);
       const int slot = ns[j];
 #pragma unroll
       for (int o = 0; o < A; o++) {
         if (o < ar2) {
           const int v = tab[q + 1 + o];
-          p.args[(int64_t)slot * A + o] = v >= 0 ? ps[v] : ns[-1 - v];
+          p.args[(int64_t)slot * A + o] = v >= 0 ? pslot(v) : ns[-1 - v];
         }
       }
       p.hss[slot] = sym;
@@ -595,17 +691,20 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
     }
     // the redex root is overwritten in place
     if (var_root) {
-      const int src = ps[rootpat];
-      int sh = p.hss[src];
+      const int src = pslot(rootpat);
+      // a variable directly below the root: its symbol and entries were read
+      // with the argument states
+      const int jr = (int)((d1 >> (3 * rootpat)) & 7);
+      int sh = jr ? ch[jr - 1] : p.hss[src];
       if ((unsigned)sh >= (unsigned)a.n_sym) {
         st(&cnt->err, -9);
         sh = 0;
       }
-      const int sar = tab[TAB_SYM + sh] & 0xff;
+      const int sar = SYM_ARITY(tab[TAB_SYM + sh]);
 #pragma unroll
       for (int j = 0; j < A; j++) {
         if (j < sar) {
-          const int cj = p.args[(int64_t)src * A + j];
+          const int cj = jr ? gc[(jr - 1) * A + j] : p.args[(int64_t)src * A + j];
           p.args[(int64_t)s * A + j] = cj;
           if ((unsigned)cj < (unsigned)N) {
             atomicAdd(&p.rc[cj], 1);
@@ -618,23 +717,23 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
       p.hss[s] = sh;
       p.state[s] = pend_nf;
       if (track) p.lastchg[s] = R.r;
-      if (R.mode == 1) notify_parent(a, L, R, s);
+      if (R.mode == 1) note = notify_parent(a, R, par_s);
       if (R.mode == 0 && a.use_memo) wake_parent(a, R, s);
       if (frontier) qpush(L, L.qr, s, N);
     } else {
-      const int rar = tab[TAB_SYM + rsym] & 0xff;
+      const int rar = SYM_ARITY(tab[TAB_SYM + rsym]);
 #pragma unroll
       for (int o = 0; o < A; o++) {
         if (o < rar) {
           const int v = tab[ro + o];
-          p.args[(int64_t)s * A + o] = v >= 0 ? ps[v] : ns[-1 - v];
+          p.args[(int64_t)s * A + o] = v >= 0 ? pslot(v) : ns[-1 - v];
         }
       }
       p.hss[s] = rsym;
       if (track) p.lastchg[s] = R.r;
       if (root_nf) {
         p.state[s] = pend_nf;
-        if (R.mode == 1) notify_parent(a, L, R, s);
+        if (R.mode == 1) note = notify_parent(a, R, par_s);
         if (R.mode == 0 && a.use_memo) wake_parent(a, R, s);
         if (frontier) qpush(L, L.qr, s, N);
       } else {
@@ -666,12 +765,28 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
     // reaches zero puts the node on the dead list)
     for (int i = 0; i < npos; i++) {
       const int dw = tab[dl + i];
-      atomicAdd(&p.rc[ps[dw & 0xff]], (int)(int8_t)((dw >> 8) & 0xff));
+      atomicAdd(&p.rc[pslot(dw & 0xff)], (int)(int8_t)((dw >> 8) & 0xff));
     }
-    for (int i = 0; i < nneg; i++) {
+    // decrements: the first NEG_BATCH are all issued before any result is
+    // examined, so their latencies (and the parent exchange's) overlap
+    constexpr int NEG_BATCH = 4;
+    ivec4 dold, dslot;
+#pragma unroll
+    for (int i = 0; i < NEG_BATCH; i++) {
+      if (i < nneg) {
+        const int dw = tab[dl + npos + i];
+        const int d = (int)(int8_t)((dw >> 8) & 0xff);
+        dslot[i] = pslot(dw & 0xff);
+        dold[i] = atomicAdd(&p.rc[dslot[i]], d) + d;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NEG_BATCH; i++)
+      if (i < nneg && dold[i] == 0) qpush(L, L.qd, dslot[i], N);
+    for (int i = NEG_BATCH; i < nneg; i++) {
       const int dw = tab[dl + npos + i];
       const int d = (int)(int8_t)((dw >> 8) & 0xff);
-      const int slot = ps[dw & 0xff];
+      const int slot = pslot(dw & 0xff);
       const int old = atomicAdd(&p.rc[slot], d);
       if (old + d == 0) qpush(L, L.qd, slot, N);
     }
@@ -680,10 +795,11 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
     C.nfset++;
     p.state[s] = pend_nf;
     if (track) p.lastchg[s] = R.r;
-    if (R.mode == 1) notify_parent(a, L, R, s);
+    if (R.mode == 1) note = notify_parent(a, R, par_s);
     if (R.mode == 0 && a.use_memo) wake_parent(a, R, s);
     if (frontier) qpush(L, L.qr, s, N);
   }
+  if (note) qpush(L, L.qf, note, N);
   // per-rule counts: one LDS atomic per distinct rule among the wave's lanes
   // (every lane of the wave runs this loop; its trip count is uniform)
   {
@@ -697,9 +813,9 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
       pending &= ~same;
     }
   }
-  tmark(a, R.r, 9);
+  tmark(a, L, R.r, 9);
   qflush(L, N);
-  tmark(a, R.r, 10);
+  tmark(a, L, R.r, 10);
 }
 
 // Collect dead node d: drop one reference to each argument, mark the slot
@@ -713,7 +829,7 @@ __device__ __forceinline__ int collect(const RoundArgs &a, const Lds &L, RoundCn
     return 0;
   }
   const int f = p.hss[d];
-  const int ar = ((unsigned)f < (unsigned)a.n_sym) ? (L.tab[TAB_SYM + f] & 0xff) : 0;
+  const int ar = ((unsigned)f < (unsigned)a.n_sym) ? SYM_ARITY(L.tab[TAB_SYM + f]) : 0;
 #pragma unroll
   for (int j = 0; j < A; j++) {
     if (j < ar) {
@@ -824,12 +940,21 @@ __device__ __forceinline__ RoundState round_state(const RoundArgs &a, int r) {
 // (plain loads: it was written before this launch began); otherwise thread 0
 // derives round r from the counters of round r-1.
 __device__ __forceinline__ RoundState round_prepare(const RoundArgs &a, const Lds &L, int r,
-                                                    bool from_pub) {
+                                                    bool from_pub, bool load_tab = false) {
   int32_t *bc = L.misc + 40;  // [40..49]
+  // the published line and (load_tab) the tables are read together: one
+  // dependent read at the start of a launch instead of two
+  int4 x, y, z;
+  if (from_pub && threadIdx.x == 0) {
+    const int4 *pp = reinterpret_cast<const int4 *>(a.ctl->pub);
+    x = pp[0];
+    y = pp[1];
+    z = pp[2];
+  }
+  if (load_tab)
+    for (int i = threadIdx.x; i < a.tab_words; i += blockDim.x) L.tab[i] = a.tab[i];
   if (threadIdx.x == 0) {
     if (from_pub) {
-      const int4 *pp = reinterpret_cast<const int4 *>(a.ctl->pub);
-      const int4 x = pp[0], y = pp[1], z = pp[2];
       bc[0] = x.x;
       bc[1] = x.y;
       bc[2] = x.z;
@@ -854,7 +979,7 @@ __device__ __forceinline__ RoundState round_prepare(const RoundArgs &a, const Ld
       bc[9] = (t.stop ? 1 : 0) | (t.quiescent ? 2 : 0) | (t.stall ? 4 : 0) | (t.err << 8);
     }
   }
-  __syncthreads();
+  lds_sync();
   RoundState rs;
   const int B = blockDim.x;
   rs.done = bc[0] != 0;
@@ -869,8 +994,8 @@ __device__ __forceinline__ RoundState round_prepare(const RoundArgs &a, const Ld
   rs.quiescent = bc[9] & 2;
   rs.stall = bc[9] & 4;
   rs.err = bc[9] >> 8;
-  __syncthreads();
-  tmark(a, rs.r, 0);
+  lds_sync();
+  tmark(a, L, rs.r, 0);
   rs.full = !rs.quiescent && (a.mode == 0 || rs.nfront == 0 || rs.r == 0 || rs.stall ||
                               (a.sweep_every > 0 && rs.r % a.sweep_every == 0));
   rs.nlist = rs.nd + (rs.full ? 0 : rs.nret + rs.nfront);
@@ -915,7 +1040,7 @@ __device__ __forceinline__ void round_execute(const RoundArgs &a, Lds &L, const 
   const bool full = rs.full, quiescent = rs.quiescent;
   const int nlist = rs.nlist, ntiles = rs.ntiles, need = rs.need;
   const int G = gridDim.x;
-  tmark(a, r, 1);
+  tmark(a, L, r, 1);
   if (a.wgtrace && r == a.wgtrace_round && tid == 0 && wg < 4096)
     a.wgtrace[wg * 8 + 4] = (long long)wall_clock64();
   if (wg == 0 && tid == 0) {
@@ -959,13 +1084,15 @@ __device__ __forceinline__ void round_execute(const RoundArgs &a, Lds &L, const 
   const int32_t *RT = ((r - 1) & 1) ? p.ret1 : p.ret0;
   const unsigned ep = (unsigned)((r - 1) & 1);
 
-  tmark(a, r, 2);
+  tmark(a, L, r, 2);
   // ---- 1. list items: collection, marker retirement, frontier slots
   {
     const int nr_here = full ? 0 : nret;
     for (int base = wg * B; base < nlist; base += Ga * B) {
       const int i = base + tid;
       int s = 0, memo = 0, fslot = 0;
+      Pre<A> pre;
+      pre.have = false;
       if (i < nd) {
         fslot = collect<A>(a, L, cnt, D[i], C);
       } else if (i < nd + nr_here) {
@@ -975,6 +1102,14 @@ __device__ __forceinline__ void round_execute(const RoundArgs &a, Lds &L, const 
         const int x = F[i - nd - nr_here];
         if ((unsigned)x < (unsigned)p.N && x > 0) {
           unsigned st = p.state[x];
+          // queued slots are mostly live and not normal forms: their
+          // symbol, entries and parent hint are read with the state, one
+          // dependent read less
+          pre.have = true;
+          pre.f = p.hss[x];
+#pragma unroll
+          for (int j = 0; j < A; j++) pre.raw[j] = p.args[(int64_t)x * A + j];
+          pre.par = R.mode == 1 ? p.par[x] : 0;
           if ((st & ST_PEND) && ((st >> 2) & 1u) != R.e) {  // retire its own marker
             st = (st & ST_NF) ? ST_NF : ST_ACTIVE;
             p.state[x] = (uint8_t)st;
@@ -987,11 +1122,11 @@ __device__ __forceinline__ void round_execute(const RoundArgs &a, Lds &L, const 
           }
         }
       }
-      process_slot<A>(a, L, R, s, memo, false, fslot, SQ, fsQ, C);
+      process_slot<A>(a, L, R, s, memo, false, fslot, SQ, fsQ, C, pre);
     }
   }
 
-  tmark(a, r, 3);
+  tmark(a, L, r, 3);
   const bool wgt = a.wgtrace && r == a.wgtrace_round && tid == 0 && wg < 4096;
   if (wgt) {
     a.wgtrace[wg * 8 + 0] = (long long)wall_clock64();
@@ -1035,7 +1170,7 @@ __device__ __forceinline__ void round_execute(const RoundArgs &a, Lds &L, const 
         vs = load_bytes(p.state + base, npt);
         if (wake_sweep) vw = load_bytes(p.wake + base, npt);
       }
-      if (t == t_first) tmark(a, r, 12);
+      if (t == t_first) tmark(a, L, r, 12);
       // state bytes of this thread's slots, kept in four registers
       ivec4 sw;
       sw[0] = (int)vs.x;
@@ -1092,7 +1227,7 @@ __device__ __forceinline__ void round_execute(const RoundArgs &a, Lds &L, const 
           }
         }
       }
-      if (t == t_first) tmark(a, r, 13);
+      if (t == t_first) tmark(a, L, r, 13);
       // sleeping slots that stay asleep: no wake bit of an earlier round
       // (plain mode), or the memo argument still not a visible normal form
       int still = 0;
@@ -1138,10 +1273,10 @@ __device__ __forceinline__ void round_execute(const RoundArgs &a, Lds &L, const 
           L.work[pos++] = (base + j) | (memo << 29);
         }
       }
-      __syncthreads();
+      lds_sync();
       int W = L.misc[0];
-      __syncthreads();  // every thread has read the count before it changes
-      if (t == t_first) tmark(a, r, 14);
+      lds_sync();  // every thread has read the count before it changes
+      if (t == t_first) tmark(a, L, r, 14);
       // examine in full passes of B slots while at least B are waiting; the
       // rest carries over to the next tile (the list holds a tile plus B),
       // and after the last tile everything is examined
@@ -1149,19 +1284,21 @@ __device__ __forceinline__ void round_execute(const RoundArgs &a, Lds &L, const 
       while (W >= B || (last && W > 0)) {
         const int take = min(W, B);
         const int wv = tid < take ? L.work[W - take + tid] : 0;
-        __syncthreads();
+        lds_sync();
         if (tid == 0) L.misc[0] = W - take;
+        Pre<A> none;
+        none.have = false;
         process_slot<A>(a, L, R, wv & 0x1fffffff, (int)((unsigned)wv >> 29), true, 0, SQ, fsQ,
-                        C);
+                        C, none);
         W -= take;
       }
-      if (t == t_first) tmark(a, r, 15);
+      if (t == t_first) tmark(a, L, r, 15);
       ntile_done++;
       nitems += exam ? __popc(exam) : 0;
     }
   }
 
-  tmark(a, r, 4);
+  tmark(a, L, r, 4);
   if (wgt) {
     a.wgtrace[wg * 8 + 1] = (long long)wall_clock64();
     a.wgtrace[wg * 8 + 2] = ntile_done;
@@ -1193,7 +1330,7 @@ __device__ __forceinline__ void round_execute(const RoundArgs &a, Lds &L, const 
       if (st) atomicAdd(&L.lstat[STAT_TRACE], (unsigned long long)st);
     }
   }
-  __syncthreads();
+  lds_sync();
   if (tid == 0 && L.misc[32]) {
     st(&cnt->active, 1);
     L.misc[32] = 0;
@@ -1202,8 +1339,10 @@ __device__ __forceinline__ void round_execute(const RoundArgs &a, Lds &L, const 
     st(&cnt->prog, 1);
     L.misc[33] = 0;
   }
+  // end of the round: every wave's global writes complete before the
+  // workgroup goes on (workgroup 0 may run the next round itself)
   __syncthreads();
-  tmark(a, r, 5);
+  tmark(a, L, r, 5);
   if (a.wgtrace && r == a.wgtrace_round && tid == 0 && wg < 4096)
     a.wgtrace[wg * 8 + 5] = (long long)wall_clock64();
 }
@@ -1213,7 +1352,7 @@ __device__ __forceinline__ void round_execute(const RoundArgs &a, Lds &L, const 
 __device__ __forceinline__ void flush_stats(const RoundArgs &a, const Lds &L) {
   Ctl *ctl = a.ctl;
   const int wg = blockIdx.x, tid = threadIdx.x;
-  __syncthreads();
+  lds_sync();
   if (tid == 0) {
     const int sp = wg & (CTL_SPREAD - 1);
     for (int k = 0; k < CTL_NSTAT; k++)
@@ -1246,27 +1385,24 @@ __device__ __forceinline__ Lds setup_lds(const RoundArgs &a, int32_t *smem, bool
   L.pf = reinterpret_cast<uint4 *>(q + 3 * qc);
   L.misc = q + 3 * qc + 8 * B;
   L.lstat = reinterpret_cast<unsigned long long *>(L.misc + 64);
-  L.rcnt = L.misc + 64 + 2 * 16;
+  L.tstamp = reinterpret_cast<unsigned long long *>(L.misc + 64 + 2 * 16);
+  L.rcnt = L.misc + 64 + 2 * 16 + 2 * TRACE_FIELDS;
   if (load_tab)
     for (int i = threadIdx.x; i < a.tab_words; i += B) L.tab[i] = a.tab[i];
-  for (int i = threadIdx.x; i < 64 + 2 * 16; i += B) L.misc[i] = 0;
+  for (int i = threadIdx.x; i < 64 + 2 * 16 + 2 * TRACE_FIELDS; i += B) L.misc[i] = 0;
   for (int i = threadIdx.x; i < a.n_rules; i += B) L.rcnt[i] = 0;
-  __syncthreads();
+  lds_sync();
   return L;
 }
 
 __device__ __forceinline__ int bcast(const Lds &L, int v) {
   if (threadIdx.x == 0) L.misc[31] = v;
-  __syncthreads();
+  lds_sync();
   const int x = L.misc[31];
-  __syncthreads();
+  lds_sync();
   return x;
 }
 
-__device__ __forceinline__ void load_tables(const RoundArgs &a, const Lds &L) {
-  for (int i = threadIdx.x; i < a.tab_words; i += blockDim.x) L.tab[i] = a.tab[i];
-  __syncthreads();
-}
 
 // One launch executes round ctl->r_cur on the whole grid.  When that round
 // is small enough for one workgroup, workgroup 0 runs it alone and then keeps
@@ -1278,14 +1414,15 @@ template <int A>
 __global__ void __launch_bounds__(1024) k_round(RoundArgs a) {
   extern __shared__ int32_t smem[];
   Ctl *ctl = a.ctl;
-  Lds L = setup_lds(a, smem, false);  // tables are loaded only by workgroups with work
+  Lds L = setup_lds(a, smem, false);
   const int wg = blockIdx.x, tid = threadIdx.x;
   // the first round of this launch, as published by the previous launch.
   // Workgroups beyond the number it uses leave at once, without reading any
   // round counter (workgroup 0 may be running later rounds alone) and
   // without a ticket, so a launch costs as many control atomics as
   // workgroups at work, however large its grid.
-  RoundState rs = round_prepare(a, L, 0, true);
+  RoundState rs = round_prepare(a, L, 0, true, true);
+  int r_exec = rs.r;  // the last round this workgroup executed (phase trace)
   if (rs.done) return;
   const int need0 = rs.need;
   if (wg >= need0) return;
@@ -1295,19 +1432,23 @@ __global__ void __launch_bounds__(1024) k_round(RoundArgs a) {
       return;
     }
     const bool alone = rs.need == 1;
-    load_tables(a, L);
     // one call site: the first round, then (workgroup 0 alone) the
     // following small rounds
     for (int k = 0;; k++) {
       round_execute<A>(a, L, rs);
+      r_exec = rs.r;
       if (!alone || k + 1 >= a.cont_rounds) break;
+      tflush(a, L, r_exec);
       rs = round_prepare(a, L, rs.r + 1, false);
       if (rs.stop) {
         flush_stats(a, L);
         if (tid == 0) round_stop(a, rs);
         return;
       }
-      if (rs.need != 1) break;
+      if (rs.need != 1) {
+        if (tid == 0 && a.trace_max) L.tstamp[0] = 0;  // a round left to the next launch
+        break;
+      }
     }
     flush_stats(a, L);
     if (alone && tid == 0)
@@ -1327,16 +1468,20 @@ __global__ void __launch_bounds__(1024) k_round(RoundArgs a) {
     const int t = atomicAdd(&ctl->ticket, 1);
     if (t == min(need0, (int)gridDim.x) - 1) {
       // last working workgroup of the launch: every round it covered is
-      // complete
-      __threadfence();
+      // complete.  It reads only counters kept with agent-scope atomics, so
+      // it needs no fence either.
       const int rr = max(ld(&ctl->r_cur) + 1, ld(&ctl->r_reached));
       const RoundState nx = round_state(a, rr);
       publish(ctl, nx);
-      tmark_any(a, rr - 1, 11);
+      if (a.trace_max)
+        L.tstamp[11] = wall_clock64();
+      else
+        tmark_any(a, rr - 1, 11);
       __hip_atomic_store(&ctl->next_need, nx.need, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_store(&ctl->ticket, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_store(&ctl->r_cur, rr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+    tflush(a, L, r_exec);
   }
 }
 
@@ -1409,7 +1554,7 @@ __global__ void __launch_bounds__(1024) k_persistent(RoundArgs a) {
 size_t trs_round_lds_bytes(int block, int npt, int tab_words, int n_rules) {
   size_t words = (size_t)((tab_words + 3) & ~3) + (size_t)block * npt + block +
                  (size_t)3 * QBUF_PER_THREAD * block + (size_t)8 * block + 64 + 2 * 16 +
-                 (size_t)n_rules;
+                 2 * TRACE_FIELDS + (size_t)n_rules;
   return words * sizeof(int32_t);
 }
 

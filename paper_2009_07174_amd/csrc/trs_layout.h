@@ -43,7 +43,10 @@
 // ---------------------------------------------------------------- tables
 // Compiled rule tables (int32 words), loaded into LDS by every workgroup.
 //   [0] n_sym  [1] n_rules  [2] A  [3] total words
-//   [TAB_SYM + f]                       symbol word: arity | nrules<<8 | first<<16
+//   [TAB_SYM + f]                       symbol word: arity | deep<<3 | nrules<<8 |
+//                                       first<<16 (deep: bit j set when some
+//                                       rule of f has a pattern below its
+//                                       argument j)
 //   [TAB_SYM + n_sym + r]               word offset of rule r's program
 // Rule program at offset p:
 //   p+0  npat | nnew<<4 | var_root<<8 | root_nf<<9 | root_ready<<10 | npos<<12 |
@@ -70,9 +73,11 @@
 // bucket the age bucket, is 1 when the node is kept.  n_sym*16 words.
 #define TAB_GATE_MAX_WORDS 4096
 
-static inline int32_t tab_sym_word(int32_t arity, int32_t nrules, int32_t first) {
-  return arity | (nrules << 8) | (first << 16);
+static inline int32_t tab_sym_word(int32_t arity, int32_t nrules, int32_t first, int32_t deep) {
+  return arity | (deep << 3) | (nrules << 8) | (first << 16);
 }
+#define SYM_ARITY(w) ((w) & 7)
+#define SYM_DEEP(w) (((w) >> 3) & 31)
 
 // ---------------------------------------------------------------- control
 #define CTL_SPREAD 64    // statistics counters are spread over this many words
