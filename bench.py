@@ -178,6 +178,7 @@ def main():
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--npt", type=int, default=0)
     ap.add_argument("--max-grid", type=int, default=0, help="workgroups per launch cap (0 = default)")
+    ap.add_argument("--pf-depth", type=int, default=0, help="sweep tiles prefetched (0 = as fit)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default (or given) block and nodes per thread")
@@ -207,14 +208,17 @@ def main():
         ctx.set_predictor(load_predictor(w, args.weights))
     opts = T.Options(block=args.block, nodes_per_thread=args.npt, mode=MODES[args.mode],
                      persistent=1 if args.persistent else 0, threshold=args.threshold,
-                     max_grid=args.max_grid)
+                     max_grid=args.max_grid, pf_depth=args.pf_depth)
     tune = None
     if not args.no_autotune and not args.block and not args.npt:
-        # the launch shape is tuned on the parent-notification frontier (six
-        # complete runs, seconds each) and used for every mode
-        log("[bench] autotuning block and nodes per thread (frontier mode)")
-        tuned, tune = ctx.autotune(T.Options(mode=T.TRS_MODE_FRONTIER, threshold=args.threshold))
+        # the launch shape is tuned on complete runs (seconds each): on the
+        # parent-notification frontier for the frontier and learned modes,
+        # on the plain sweep for plain mode
+        tmode = T.TRS_MODE_PLAIN if args.mode == "plain" else T.TRS_MODE_FRONTIER
+        log(f"[bench] autotuning the launch shape (mode {tmode})")
+        tuned, tune = ctx.autotune(T.Options(mode=tmode, threshold=args.threshold))
         opts.block, opts.nodes_per_thread = tuned.block, tuned.nodes_per_thread
+        opts.max_grid = tuned.max_grid
         log(f"[bench] autotune: {tune}")
     stream = torch.cuda.current_stream()
     for i in range(args.warmup):
@@ -264,6 +268,7 @@ def main():
         "config": {"workload": w.name, "terms": w.n_terms, "initial_nodes": w.initial_nodes,
                    "pool_slots": w.pool_slots, "maxarity": A, "mode": args.mode,
                    "persistent": bool(args.persistent), "block": opts.block,
+                   "max_grid": opts.max_grid,
                    "nodes_per_thread": opts.nodes_per_thread},
         "autotune": tune,
         "rule_apps": apps,
@@ -289,7 +294,14 @@ def main():
         res["compare"] = {}
         for m in compare:
             o = T.Options(block=opts.block, nodes_per_thread=opts.nodes_per_thread, mode=MODES[m],
-                          persistent=1 if args.persistent else 0, threshold=args.threshold)
+                          persistent=1 if args.persistent else 0, threshold=args.threshold,
+                          max_grid=opts.max_grid)
+            if m == "plain" and tune is not None:
+                # the plain sweep has launch shapes of its own (full sweeps
+                # every round: wide workgroups, about one per compute unit)
+                log("[bench] autotuning the plain sweep's launch shape")
+                o, tune_m = ctx.autotune(o)
+                log(f"[bench] autotune plain: {tune_m}")
             torch.cuda.synchronize()
             t1 = time.perf_counter()
             sm = ctx.normalize(o)
@@ -304,7 +316,9 @@ def main():
                 "node_visits": sm["node_visits"], "node_visits_per_s": sm["node_visits"] / wm,
                 "full_sweeps": sm["full_sweeps"], "speedup_of_" + args.mode: wm / (wall / args.steps),
                 "algorithmic_gbps": algorithmic_bytes(sm, A)["total"] / wm / 1e9,
-                "roofline_frac": algorithmic_bytes(sm, A)["total"] / wm / 1e9 / HBM_PEAK_GBPS}
+                "roofline_frac": algorithmic_bytes(sm, A)["total"] / wm / 1e9 / HBM_PEAK_GBPS,
+                "block": o.block, "nodes_per_thread": o.nodes_per_thread,
+                "max_grid": o.max_grid, "us_per_round": 1e6 * wm / max(sm["rounds"], 1)}
     if compare:
         # speedups over the plain sweep (the paper's method), from the time
         # of one normalisation in each mode

@@ -117,6 +117,9 @@ typedef struct {
                                 compute unit); larger grids keep more sweep
                                 tiles in flight, smaller ones fewer idle
                                 workgroups in frontier rounds */
+  int32_t pf_depth;          /* with 16 nodes per thread: most sweep tiles a
+                                workgroup copies ahead into LDS (1..4; 0 = as
+                                many as fit, at most 4) */
 } trs_opts;
 
 typedef struct {
@@ -182,13 +185,17 @@ int64_t trs_device_bytes(int64_t pool_slots, int32_t maxarity);
 /* Default options (mode plain, tuned block and nodes per thread). */
 void trs_default_opts(trs_opts *opts);
 
-/* Autotuner of the launch shape (the batching step: block size and nodes per
- * thread).  Times trs_normalize of the loaded terms under *base, first over
- * block sizes 128, 256, 512, 1024 at 16 nodes per thread, then over 4 and 8
- * nodes per thread at the best block (six complete normalisations).  *best
- * receives *base with the fastest block and nodes_per_thread.  The result is cached per context and loaded terms (a
- * second call with the same mode returns it without trials; res->trials = 0
- * then).  After the call the context holds a completed normalisation. */
+/* Autotuner of the launch shape (the batching step: block size, nodes per
+ * thread and, for the plain sweep, the grid).  Times complete trs_normalize
+ * runs of the loaded terms under *base.  Frontier and learned modes: block
+ * sizes 128, 256, 512, 1024 at 16 nodes per thread, then 4 and 8 nodes per
+ * thread at the best block (six runs, default grid).  Plain mode, whose
+ * rounds are full sweeps: (block, grid) in (1024, 256), (512, 256),
+ * (256, 512), (1024, 512) at 16 nodes per thread (four runs).  *best
+ * receives *base with the fastest block, nodes_per_thread and max_grid.  The
+ * result is cached per context and loaded terms (a second call with the same
+ * mode returns it without trials; res->trials = 0 then).  After the call the
+ * context holds a completed normalisation. */
 typedef struct {
   int32_t trials;       /* configurations timed by this call */
   int32_t best_block;
@@ -197,6 +204,9 @@ typedef struct {
   double best_ms;       /* device time of the fastest trial */
   int32_t block[8], npt[8];
   double ms[8];         /* device time per trial */
+  int32_t best_grid;    /* max_grid of the fastest trial (0 = default) */
+  int32_t pad2;
+  int32_t grid[8];
 } trs_tune_result;
 
 trs_status trs_autotune(trs_ctx *ctx, const trs_opts *base, trs_opts *best,

@@ -27,6 +27,12 @@ const char *kStatusText[] = {"ok",         "bad argument", "call out of order", 
 
 }  // namespace
 
+// A launch shape chosen by the autotuner and its device time.
+struct Tuned {
+  int block, npt, grid;
+  double ms;
+};
+
 struct trs_ctx {
   trs_config cfg{};
   int A = 0;
@@ -85,7 +91,7 @@ struct trs_ctx {
   int32_t *d_trace_n = nullptr;
   int64_t trace_alloc = 0, trace_count = 0;
   // autotuner results for the loaded terms, per mode: block, npt, ms
-  std::map<int, std::tuple<int, int, double>> tuned;
+  std::map<int, Tuned> tuned;  // autotuned launch shape per mode
 
   // results of the last normalisation
   bool normalized = false;
@@ -344,6 +350,9 @@ trs_status compile_rule(int rid, const std::vector<int32_t> &arity,
       return (ctx)->fail(TRS_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
+// two wake bits per slot, in 32-bit words, over the slots a sweep may read
+size_t wake_bytes(int64_t N) { return (size_t)((N + (1 << 16)) / 16 + 1) * 4; }
+
 struct Piece {
   void **dst;
   size_t bytes;
@@ -375,7 +384,7 @@ std::vector<Piece> device_pieces(trs_ctx *c, int64_t N, int A) {
       {(void **)&c->pool.ret0, (size_t)N * 4},
       {(void **)&c->pool.ret1, (size_t)N * 4},
       {(void **)&c->pool.qstamp, (size_t)N * 4},
-      {(void **)&c->pool.wake, (size_t)N + state_pad},
+      {(void **)&c->pool.wake, wake_bytes(N)},
   };
 }
 
@@ -469,6 +478,7 @@ void trs_default_opts(trs_opts *o) {
   o->label_horizon = 0;
   o->sweep_every = 0;
   o->max_grid = 0;
+  o->pf_depth = 0;
 }
 
 trs_status trs_create(trs_ctx **out, const trs_config *cfg) {
@@ -694,6 +704,7 @@ trs_status trs_normalize(trs_ctx *c, const trs_opts *opts_in, trs_stats *stats) 
   if (o.trace < 0 || o.trace > 65536) return c->fail(TRS_E_ARG, "trace rate must be 0..65536");
   if (o.max_grid < 0 || o.max_grid > (1 << 20))
     return c->fail(TRS_E_ARG, "max_grid must be 0..2^20");
+  if (o.pf_depth < 0 || o.pf_depth > 4) return c->fail(TRS_E_ARG, "pf_depth must be 0..4");
   if (o.label_horizon < 0 || o.sweep_every < -1)
     return c->fail(TRS_E_ARG, "label_horizon must be >= 0, sweep_every >= -1");
   if (o.trace && o.mode != TRS_MODE_PLAIN)
@@ -730,7 +741,7 @@ trs_status trs_normalize(trs_ctx *c, const trs_opts *opts_in, trs_stats *stats) 
   HIPCHK(c, hipMemcpyAsync(c->pool.state, c->d_img_state, M1, hipMemcpyDeviceToDevice, s));
   HIPCHK(c, hipMemcpyAsync(c->pool.par, c->d_img_par, M1 * 4, hipMemcpyDeviceToDevice, s));
   if (o.mode == TRS_MODE_PLAIN)
-    HIPCHK(c, hipMemsetAsync(c->pool.wake, 0, (size_t)c->cfg.pool_slots, s));
+    HIPCHK(c, hipMemsetAsync(c->pool.wake, 0, wake_bytes(c->cfg.pool_slots), s));
   HIPCHK(c, hipMemcpyAsync(c->d_tab, c->tab.data(), c->tab.size() * 4, hipMemcpyHostToDevice, s));
   std::memset(c->h_ctl, 0, sizeof(Ctl));
   c->h_ctl->n[0] = (int32_t)M1;
@@ -872,7 +883,21 @@ trs_status trs_normalize(trs_ctx *c, const trs_opts *opts_in, trs_stats *stats) 
       ra.wgtrace = d_wgt;
     }
   }
-  const size_t lds = trs_round_lds_bytes(B, npt, ra.tab_words, c->n_rules);
+  // LDS list buffers: four entries per thread for small workgroups, two for
+  // large ones (whose LDS goes to the sweep); with 16 slots per thread the
+  // sweep copies tiles ahead into an LDS ring, as deep (up to 4) as fits
+  ra.qbuf = B >= 512 ? 2 : 4;
+  ra.pf_depth = 0;
+  if (npt == 16) {
+    const int want = o.pf_depth > 0 ? o.pf_depth : 4;
+    for (int d = want; d >= 1; d--) {
+      if (trs_round_lds_bytes(B, npt, ra.tab_words, c->n_rules, d, ra.qbuf) <= 160 * 1024) {
+        ra.pf_depth = d;
+        break;
+      }
+    }
+  }
+  const size_t lds = trs_round_lds_bytes(B, npt, ra.tab_words, c->n_rules, ra.pf_depth, ra.qbuf);
   if (lds > 160 * 1024) return c->fail(TRS_E_ARG, "configuration needs too much LDS");
   const int TILE = B * npt;
   HIPCHK(c, trs_prepare_kernels(A, lds));
@@ -1118,50 +1143,62 @@ trs_status trs_autotune(trs_ctx *c, const trs_opts *base, trs_opts *best, trs_tu
   auto it = c->tuned.find(base->mode);
   if (it != c->tuned.end()) {
     *best = *base;
-    best->block = std::get<0>(it->second);
-    best->nodes_per_thread = std::get<1>(it->second);
+    best->block = it->second.block;
+    best->nodes_per_thread = it->second.npt;
+    best->max_grid = it->second.grid;
     r.best_block = best->block;
     r.best_npt = best->nodes_per_thread;
-    r.best_ms = std::get<2>(it->second);
+    r.best_grid = best->max_grid;
+    r.best_ms = it->second.ms;
     if (res) *res = r;
     return TRS_OK;
   }
-  int bb = 0, bn = 16;
-  double bms = 0;
-  auto trial = [&](int B, int npt) -> trs_status {
+  Tuned bt{0, 16, 0, 0.0};
+  auto trial = [&](int B, int npt, int grid) -> trs_status {
     trs_opts o = *base;
     o.block = B;
     o.nodes_per_thread = npt;
+    o.max_grid = grid;
     trs_stats st;
     const trs_status s = trs_normalize(c, &o, &st);
     if (s != TRS_OK) return s;
     const int k = r.trials++;
     r.block[k] = B;
     r.npt[k] = npt;
+    r.grid[k] = grid;
     r.ms[k] = st.device_ms;
-    if (bb == 0 || st.device_ms < bms) {
-      bb = B;
-      bn = npt;
-      bms = st.device_ms;
-    }
+    if (bt.block == 0 || st.device_ms < bt.ms) bt = Tuned{B, npt, grid, st.device_ms};
     return TRS_OK;
   };
-  for (int B : {128, 256, 512, 1024}) {
-    const trs_status s = trial(B, 16);
-    if (s != TRS_OK) return s;
+  if (base->mode == TRS_MODE_PLAIN) {
+    // full sweeps every round: wide workgroups (16 waves) with a grid of
+    // about one or two per compute unit keep the most sweep tiles in flight
+    const int cu = std::max(1, c->cu_count);
+    const int shapes[4][2] = {{1024, cu}, {512, cu}, {256, 2 * cu}, {1024, 2 * cu}};
+    for (const auto &sh : shapes) {
+      const trs_status s = trial(sh[0], 16, sh[1]);
+      if (s != TRS_OK) return s;
+    }
+  } else {
+    for (int B : {128, 256, 512, 1024}) {
+      const trs_status s = trial(B, 16, 0);
+      if (s != TRS_OK) return s;
+    }
+    const int B0 = bt.block;
+    for (int npt : {4, 8}) {
+      const trs_status s = trial(B0, npt, 0);
+      if (s != TRS_OK) return s;
+    }
   }
-  const int B0 = bb;
-  for (int npt : {4, 8}) {
-    const trs_status s = trial(B0, npt);
-    if (s != TRS_OK) return s;
-  }
-  c->tuned[base->mode] = std::make_tuple(bb, bn, bms);
+  c->tuned[base->mode] = bt;
   *best = *base;
-  best->block = bb;
-  best->nodes_per_thread = bn;
-  r.best_block = bb;
-  r.best_npt = bn;
-  r.best_ms = bms;
+  best->block = bt.block;
+  best->nodes_per_thread = bt.npt;
+  best->max_grid = bt.grid;
+  r.best_block = bt.block;
+  r.best_npt = bt.npt;
+  r.best_grid = bt.grid;
+  r.best_ms = bt.ms;
   if (res) *res = r;
   return TRS_OK;
 }

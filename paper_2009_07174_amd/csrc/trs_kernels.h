@@ -13,6 +13,9 @@ struct RoundArgs {
   int32_t n_sym;
   int32_t n_rules;
   int32_t npt;          // slots per thread per tile
+  int32_t pf_depth;     // sweep tiles copied ahead into LDS (0: none; 1..4
+                        // with 16 slots per thread)
+  int32_t qbuf;         // LDS entries per thread of each list buffer
   int32_t nrounds;      // rounds a persistent launch may run
   int32_t cont_rounds;  // rounds workgroup 0 may continue alone in one launch
   int32_t small_cap;    // list items one workgroup takes on alone
@@ -49,7 +52,8 @@ struct RoundArgs {
 #define TRACE_FIELDS 16
 
 // LDS bytes a round kernel needs for this configuration.
-size_t trs_round_lds_bytes(int block, int npt, int tab_words, int n_rules);
+size_t trs_round_lds_bytes(int block, int npt, int tab_words, int n_rules, int pf_depth,
+                           int qbuf);
 
 // Sets kernel attributes (dynamic LDS above 64 KiB); call before launching
 // or capturing with a given LDS size.

@@ -51,7 +51,6 @@
 
 #define MAXPAT 8
 #define MAXNEW 8
-#define QBUF_PER_THREAD 4
 
 namespace {
 
@@ -156,7 +155,8 @@ struct Lds {
   //       [63] barrier flag
   int32_t *misc;
   int32_t *rcnt;  // per-rule application counts of this workgroup
-  uint4 *pf;      // sweep prefetch: 16 state bytes ([0, B)) and 16 wake bytes
+  uint4 *pf;      // sweep prefetch ring: 16 state bytes per thread and buffer
+  uint32_t *pfw;  // and the matching wake word (32 bits: 16 slots)
                   // ([B, 2B)) per thread for the next tile
   // statistics of this workgroup over every round it runs in the launch,
   // flushed once at the end of the launch: STAT_* then gc rounds, full
@@ -354,20 +354,27 @@ __device__ __forceinline__ int notify_parent(const RoundArgs &a, const RoundCtx 
 
 typedef __attribute__((address_space(3))) void lds_void;
 
-// This wave's prefetch entries (state: which = 0, wake: which = 1), from
-// wave-uniform values only, so that the address stays in scalar registers
-// (a spilled vector address would be reloaded, and the wait for that reload
-// would also wait for the prefetch just issued).
-__device__ __forceinline__ uint4 *pf_wave(const Lds &L, int which) {
+// This wave's prefetch entries in ring buffer b (state bytes, wake words),
+// from wave-uniform values only, so that the address stays in scalar
+// registers (a spilled vector address would be reloaded, and the wait for
+// that reload would also wait for the prefetch just issued).
+__device__ __forceinline__ uint4 *pf_state(const Lds &L, int b) {
   const int w0 = __builtin_amdgcn_readfirstlane((int)threadIdx.x & ~63);
-  return L.pf + which * (int)blockDim.x + w0;
+  return L.pf + b * (int)blockDim.x + w0;
+}
+__device__ __forceinline__ uint32_t *pf_wake(const Lds &L, int b) {
+  const int w0 = __builtin_amdgcn_readfirstlane((int)threadIdx.x & ~63);
+  return L.pfw + b * (int)blockDim.x + w0;
 }
 
-// Asynchronous copy of 16 bytes per lane from global memory straight into
-// LDS (no registers held while in flight): lane l of the wave writes
+// Asynchronous copy of 16 (4) bytes per lane from global memory straight
+// into LDS (no registers held while in flight): lane l of the wave writes
 // dst_wave[l], where dst_wave is the wave's (uniform) base.
 __device__ __forceinline__ void lds_fetch16(const void *src, uint4 *dst_wave) {
   __builtin_amdgcn_global_load_lds(src, (lds_void *)dst_wave, 16, 0, 0);
+}
+__device__ __forceinline__ void lds_fetch4(const void *src, uint32_t *dst_wave) {
+  __builtin_amdgcn_global_load_lds(src, (lds_void *)dst_wave, 4, 0, 0);
 }
 
 // npt (1, 2, 4, 8 or 16) consecutive bytes, in byte order from the low end
@@ -408,10 +415,31 @@ __device__ __forceinline__ int nz7x4(unsigned x) {
 // word that holds the parent's wake byte.
 __device__ __forceinline__ void wake_parent(const RoundArgs &a, const RoundCtx &R, int s) {
   const int par = a.p.par[s];
-  if (par > 0 && par < a.p.N) {
-    unsigned *w = reinterpret_cast<unsigned *>(a.p.wake + (par & ~3));
-    atomicOr(w, (1u << R.e) << (8 * (par & 3)));
+  if (par > 0 && par < a.p.N) atomicOr(&a.p.wake[par >> 4], 1u << (((par & 15) << 1) | R.e));
+}
+
+// Wait until at most k (0..6) of the wave's vector memory operations are
+// outstanding (s_waitcnt takes the count as an immediate).
+__device__ __forceinline__ void vm_wait_tiles(int k) {
+  switch (k) {
+    case 0: asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); break;
+    case 1: asm volatile("s_waitcnt vmcnt(1)" ::: "memory"); break;
+    case 2: asm volatile("s_waitcnt vmcnt(2)" ::: "memory"); break;
+    case 3: asm volatile("s_waitcnt vmcnt(3)" ::: "memory"); break;
+    case 4: asm volatile("s_waitcnt vmcnt(4)" ::: "memory"); break;
+    case 5: asm volatile("s_waitcnt vmcnt(5)" ::: "memory"); break;
+    default: asm volatile("s_waitcnt vmcnt(6)" ::: "memory"); break;
   }
+}
+
+// Bits 0, 2, ..., 30 of x, packed into the low 16 bits.
+__device__ __forceinline__ int even_bits(unsigned x) {
+  x &= 0x55555555u;
+  x = (x | (x >> 1)) & 0x33333333u;
+  x = (x | (x >> 2)) & 0x0f0f0f0fu;
+  x = (x | (x >> 4)) & 0x00ff00ffu;
+  x = (x | (x >> 8)) & 0x0000ffffu;
+  return (int)x;
 }
 
 // Examine slot s (s <= 0: idle lane) and rewrite it if it is a redex whose
@@ -1144,33 +1172,49 @@ __device__ __forceinline__ void round_execute(const RoundArgs &a, Lds &L, const 
     // on (the bytes of a later tile cannot change meanwhile in a way that
     // matters: collection is over, and slots that become live this round
     // carry this round's marker)
-    const bool ahead = npt == 16;
+    // tiles copied ahead into an LDS ring of pf_depth buffers (each: the
+    // state bytes, then in plain mode the wake bytes)
+    const int depth = a.pf_depth;
+    const bool ahead = depth > 0;
     int t = xcd_remap(wg, Ga);
-    const int t_first = t;
-    if (ahead && t < ntiles) {
-      const int64_t b0 = (int64_t)t * TILE + tid * 16;
-      lds_fetch16(p.state + b0, pf_wave(L, 0));
-      if (wake_sweep) lds_fetch16(p.wake + b0, pf_wave(L, 1));
+    auto pf_issue = [&](int tt, int b) {
+      const int64_t b0 = (int64_t)tt * TILE + tid * 16;
+      lds_fetch16(p.state + b0, pf_state(L, b));
+      if (wake_sweep) lds_fetch4(p.wake + (b0 >> 4), pf_wake(L, b));
+    };
+    if (ahead) {
+      for (int k = 0; k < depth; k++)
+        if (t + k * Ga < ntiles) pf_issue(t + k * Ga, k);
     }
-    for (; t < ntiles; t += Ga) {
+    int Wb = 0;  // work-list items carried over from earlier tiles
+    for (int it = 0; t < ntiles; t += Ga, it++) {
+      const int b_cur = ahead ? it % depth : 0;  // ring buffer of this tile
+      // (phase trace: fields 1 and 12-15 time the third tile of the sweep, in
+      // steady state: its start, data in, classified, appended, examined)
+      if (it == 2) tmark(a, L, r, 1);
       const int base = t * TILE + tid * npt;
-      uint4 vs, vw = make_uint4(0, 0, 0, 0);
+      uint4 vs;
+      unsigned ww = 0;  // wake bits of the thread's slots, two per slot
       if (ahead) {
-        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-        vs = L.pf[tid];
-        if (wake_sweep) vw = L.pf[B + tid];
-        // the entries are read before the next tile's copy overwrites them
+        const int b = b_cur;
+        // wait for this tile's copy.  The copies of the following tiles
+        // issued so far (at most depth - 1) were the wave's last memory
+        // operations -- each issued at the end of an iteration -- and the
+        // wave's vector memory counter retires in issue order, so waiting
+        // until only their one or two operations per tile remain leaves
+        // them in flight.
+        const int ahead_tiles = min(depth - 1, (ntiles - 1 - t) / Ga);
+        vm_wait_tiles(ahead_tiles * (wake_sweep ? 2 : 1));
+        vs = L.pf[b * B + tid];
+        if (wake_sweep) ww = L.pfw[b * B + tid];
+        // the entries are read before a later copy overwrites them
         asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-        if (t + Ga < ntiles) {
-          const int64_t nb = (int64_t)(t + Ga) * TILE + tid * 16;
-          lds_fetch16(p.state + nb, pf_wave(L, 0));
-          if (wake_sweep) lds_fetch16(p.wake + nb, pf_wave(L, 1));
-        }
+        if (depth == 1 && t + Ga < ntiles) pf_issue(t + Ga, 0);  // reuses the only buffer
       } else {
         vs = load_bytes(p.state + base, npt);
-        if (wake_sweep) vw = load_bytes(p.wake + base, npt);
+        if (wake_sweep) ww = p.wake[base >> 4] >> (2 * (base & 15));
       }
-      if (t == t_first) tmark(a, L, r, 12);
+      if (it == 2) tmark(a, L, r, 12);
       // state bytes of this thread's slots, kept in four registers
       ivec4 sw;
       sw[0] = (int)vs.x;
@@ -1183,51 +1227,61 @@ __device__ __forceinline__ void round_execute(const RoundArgs &a, Lds &L, const 
       // normal form in an earlier round)
       int wmask = 0;
       if (wake_sweep) {
-        const unsigned sh = 1u - e;
-        wmask = pack4(vw.x >> sh) | pack4(vw.y >> sh) << 4 | pack4(vw.z >> sh) << 8 |
-                pack4(vw.w >> sh) << 12;
+        wmask = even_bits(ww >> (1u - e));
         if (npt < 16) wmask &= (1 << npt) - 1;
       }
-      // candidate slots, found for the 16 bytes at once: a byte whose low 7
-      // bits are not all zero (live and not a plain normal form, or a
-      // marker), within 0 < slot < n
-      int cand = nz7x4((unsigned)sw[0]) | nz7x4((unsigned)sw[1]) << 4 |
-                 nz7x4((unsigned)sw[2]) << 8 | nz7x4((unsigned)sw[3]) << 12;
-      if (npt < 16) cand &= (1 << npt) - 1;
-      if (base == 0) cand &= ~1;
+      // classification of the slots, four bytes at a time (SWAR), within
+      // 0 < slot < n:
+      //   pending  live and not in normal form: an unmarked live slot, or a
+      //            marker of the previous round (retired on the way) that is
+      //            not a normal form
+      //   memoed   an unmarked live slot with a memo
+      //   retire   a marker of the previous round (a marker of this round's
+      //            parity was created this round and is left alone)
+      int valid = npt < 16 ? (1 << npt) - 1 : 0xffff;
+      if (base == 0) valid &= ~1;
       {
         const int lim = n - base;
-        if (lim < npt) cand &= lim > 0 ? (1 << lim) - 1 : 0;
+        if (lim < npt) valid &= lim > 0 ? (1 << lim) - 1 : 0;
       }
-      // live non-normal-form slots among them (markers of the previous round
-      // are retired on the way; a retired marker carries no memo), and those
-      // with a memo; off the wake path, the recorded arguments of all of
-      // them are read first, then all their states, so the loads overlap
-      ivec16 cidx = (ivec16)(0);   // memo argument slot (0: none)
-      int pending = 0;             // bit j: slot j is live and not in normal form
-      int memoed = 0;              // bit j: slot j is live and has a memo
-      for (int m = cand; m; m &= m - 1) {
+      int pending = 0, memoed = 0, retire = 0;
+      {
+        const unsigned er = e ? 0x01010101u : 0u;
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+          const unsigned x = (unsigned)sw[q];
+          const unsigned pend = (x >> 1) & 0x01010101u;
+          const unsigned prev = pend & (((x >> 2) & 0x01010101u) ^ er);
+          const unsigned nf = (x >> 7) & 0x01010101u;
+          const unsigned live = ((x & 0x7f7f7f7fu) + 0x7f7f7f7fu) >> 7;  // low 7 bits not 0
+          const unsigned normal = live & ~pend;
+          const unsigned mem = ((x & 0x38383838u) + 0x78787878u) >> 7;   // memo bits not 0
+          pending |= pack4(normal | (prev & ~nf)) << (4 * q);
+          memoed |= pack4(normal & mem) << (4 * q);
+          retire |= pack4(prev) << (4 * q);
+        }
+      }
+      pending &= valid;
+      retire &= valid;
+      memoed = a.use_memo ? memoed & valid : 0;
+      for (int m = retire; m; m &= m - 1) {
         const int j = __builtin_ctz(m);
-        const int slot = base + j;
-        unsigned st = ((unsigned)sw[j >> 2] >> ((j & 3) * 8)) & 0xffu;
-        if (st & ST_PEND) {
-          if (((st >> 2) & 1u) == e) continue;  // created this round
-          st = (st & ST_NF) ? ST_NF : ST_ACTIVE;
-          p.state[slot] = (uint8_t)st;
-          if (st != ST_NF) pending |= 1 << j;
-          continue;
-        }
-        pending |= 1 << j;
-        if (a.use_memo && (st & ST_MEMO_MASK)) {
-          memoed |= 1 << j;
-          if (!wake_sweep) {
-            const int memo = (int)((st & ST_MEMO_MASK) >> ST_MEMO_SHIFT);
-            const int c = p.args[(int64_t)slot * A + (memo - 1)];
-            cidx[j] = ((unsigned)c < (unsigned)p.N) ? c : 0;
-          }
+        const unsigned st = ((unsigned)sw[j >> 2] >> ((j & 3) * 8)) & 0xffu;
+        p.state[base + j] = (uint8_t)((st & ST_NF) ? ST_NF : ST_ACTIVE);
+      }
+      // off the wake path, the recorded arguments of the memoed slots are
+      // read first, then all their states, so the loads overlap
+      ivec16 cidx = (ivec16)(0);  // memo argument slot (0: none)
+      if (!wake_sweep) {
+        for (int m = memoed; m; m &= m - 1) {
+          const int j = __builtin_ctz(m);
+          const unsigned st = ((unsigned)sw[j >> 2] >> ((j & 3) * 8)) & 0xffu;
+          const int memo = (int)((st & ST_MEMO_MASK) >> ST_MEMO_SHIFT);
+          const int c = p.args[(int64_t)(base + j) * A + (memo - 1)];
+          cidx[j] = ((unsigned)c < (unsigned)p.N) ? c : 0;
         }
       }
-      if (t == t_first) tmark(a, L, r, 13);
+      if (it == 2) tmark(a, L, r, 13);
       // sleeping slots that stay asleep: no wake bit of an earlier round
       // (plain mode), or the memo argument still not a visible normal form
       int still = 0;
@@ -1237,8 +1291,7 @@ __device__ __forceinline__ void round_execute(const RoundArgs &a, Lds &L, const 
         // wake a slot; a bit set in this round stays for the next one
         for (int m = memoed & wmask; m; m &= m - 1) {
           const int slot = base + __builtin_ctz(m);
-          atomicAnd(reinterpret_cast<unsigned *>(p.wake + (slot & ~3)),
-                    ~((1u << (1u - e)) << (8 * (slot & 3))));
+          atomicAnd(&p.wake[slot >> 4], ~(1u << (((slot & 15) << 1) | (1u - e))));
         }
       } else if (memoed) {
         ivec16 cst = (ivec16)(0);
@@ -1255,15 +1308,20 @@ __device__ __forceinline__ void round_execute(const RoundArgs &a, Lds &L, const 
       C.memo += __popc(still);  // still blocked by the same argument
       // the slots of this thread to examine
       const int exam = pending & ~still;
-      // append them to the LDS work list: a wave prefix sum of the counts
-      // and one LDS atomic per wave
-      {
+      // append them to the LDS work list behind the Wb waiting items: a
+      // wave prefix sum of the counts and one LDS atomic per wave (waves
+      // with nothing to append skip both); the tile's count is kept in one
+      // of three rotating LDS counters, so one barrier per tile suffices
+      // (counter it+2 is cleared after this tile's barrier: every wave has
+      // read it in tile it-1, and none appends to it before tile it+2)
+      int32_t *tcount = L.misc + 24 + it % 3;
+      if (__ballot(exam != 0)) {
         const int cnt = __popc(exam);
         const int incl = wave_incl_scan(cnt);
         const int tot = __shfl(incl, 63, 64);
         int wb = 0;
-        if (lane() == 63 && tot) wb = atomicAdd(&L.misc[0], tot);
-        int pos = __shfl(wb, 63, 64) + incl - cnt;
+        if (lane() == 63) wb = atomicAdd(tcount, tot);
+        int pos = Wb + __shfl(wb, 63, 64) + incl - cnt;
         for (int m = exam; m; m &= m - 1) {
           const int j = __builtin_ctz(m);
           const unsigned byte = ((unsigned)sw[j >> 2] >> ((j & 3) * 8)) & 0xffu;
@@ -1274,27 +1332,31 @@ __device__ __forceinline__ void round_execute(const RoundArgs &a, Lds &L, const 
         }
       }
       lds_sync();
-      int W = L.misc[0];
-      lds_sync();  // every thread has read the count before it changes
-      if (t == t_first) tmark(a, L, r, 14);
+      int W = Wb + *tcount;
+      if (tid == 0) L.misc[24 + (it + 2) % 3] = 0;
+      if (it == 2) tmark(a, L, r, 14);
       // examine in full passes of B slots while at least B are waiting; the
       // rest carries over to the next tile (the list holds a tile plus B),
       // and after the last tile everything is examined
       const bool last = t + Ga >= ntiles;
       while (W >= B || (last && W > 0)) {
+        // (process_slot's barriers order these reads before later appends
+        // over the same entries)
         const int take = min(W, B);
         const int wv = tid < take ? L.work[W - take + tid] : 0;
-        lds_sync();
-        if (tid == 0) L.misc[0] = W - take;
         Pre<A> none;
         none.have = false;
         process_slot<A>(a, L, R, wv & 0x1fffffff, (int)((unsigned)wv >> 29), true, 0, SQ, fsQ,
                         C, none);
         W -= take;
       }
-      if (t == t_first) tmark(a, L, r, 15);
+      Wb = W;
+      if (it == 2) tmark(a, L, r, 15);
       ntile_done++;
       nitems += exam ? __popc(exam) : 0;
+      // two or more buffers: the tile depth strides ahead goes into the one
+      // just read, as the iteration's last memory operation
+      if (depth >= 2 && t + depth * Ga < ntiles) pf_issue(t + depth * Ga, b_cur);
     }
   }
 
@@ -1339,6 +1401,7 @@ __device__ __forceinline__ void round_execute(const RoundArgs &a, Lds &L, const 
     st(&cnt->prog, 1);
     L.misc[33] = 0;
   }
+  if (tid == 0) L.misc[24] = L.misc[25] = L.misc[26] = 0;  // the sweep's tile counters
   // end of the round: every wave's global writes complete before the
   // workgroup goes on (workgroup 0 may run the next round itself)
   __syncthreads();
@@ -1374,7 +1437,7 @@ __device__ __forceinline__ Lds setup_lds(const RoundArgs &a, int32_t *smem, bool
   L.tab = smem;
   L.work = L.tab + ((a.tab_words + 3) & ~3);
   int32_t *q = L.work + B * a.npt + B;  // a tile's slots plus a carried-over pass
-  const int qc = QBUF_PER_THREAD * B;
+  const int qc = a.qbuf * B;
   L.qd.buf = q;
   L.qf.buf = q + qc;
   L.qr.buf = q + 2 * qc;
@@ -1383,7 +1446,8 @@ __device__ __forceinline__ Lds setup_lds(const RoundArgs &a, int32_t *smem, bool
   L.qf.slot = 2;
   L.qr.slot = 3;
   L.pf = reinterpret_cast<uint4 *>(q + 3 * qc);
-  L.misc = q + 3 * qc + 8 * B;
+  L.pfw = reinterpret_cast<uint32_t *>(q + 3 * qc + 4 * B * a.pf_depth);
+  L.misc = q + 3 * qc + 5 * B * a.pf_depth;
   L.lstat = reinterpret_cast<unsigned long long *>(L.misc + 64);
   L.tstamp = reinterpret_cast<unsigned long long *>(L.misc + 64 + 2 * 16);
   L.rcnt = L.misc + 64 + 2 * 16 + 2 * TRACE_FIELDS;
@@ -1551,9 +1615,10 @@ __global__ void __launch_bounds__(1024) k_persistent(RoundArgs a) {
 
 }  // namespace
 
-size_t trs_round_lds_bytes(int block, int npt, int tab_words, int n_rules) {
+size_t trs_round_lds_bytes(int block, int npt, int tab_words, int n_rules, int pf_depth,
+                           int qbuf) {
   size_t words = (size_t)((tab_words + 3) & ~3) + (size_t)block * npt + block +
-                 (size_t)3 * QBUF_PER_THREAD * block + (size_t)8 * block + 64 + 2 * 16 +
+                 (size_t)3 * qbuf * block + (size_t)5 * block * pf_depth + 64 + 2 * 16 +
                  2 * TRACE_FIELDS + (size_t)n_rules;
   return words * sizeof(int32_t);
 }
@@ -1601,13 +1666,13 @@ hipError_t trs_prepare_kernels(int A, size_t lds) {
 }
 
 hipError_t trs_launch_round(int A, const RoundArgs &a, int grid, int block, hipStream_t s) {
-  const size_t lds = trs_round_lds_bytes(block, a.npt, a.tab_words, a.n_rules);
+  const size_t lds = trs_round_lds_bytes(block, a.npt, a.tab_words, a.n_rules, a.pf_depth, a.qbuf);
   DISPATCH_A(A, launch_round_A, a, grid, block, lds, s);
   return hipGetLastError();
 }
 
 hipError_t trs_launch_persistent(int A, const RoundArgs &a, int grid, int block, hipStream_t s) {
-  const size_t lds = trs_round_lds_bytes(block, a.npt, a.tab_words, a.n_rules);
+  const size_t lds = trs_round_lds_bytes(block, a.npt, a.tab_words, a.n_rules, a.pf_depth, a.qbuf);
   g_coop_status = hipSuccess;
   DISPATCH_A(A, launch_pers_A, a, grid, block, lds, s);
   if (g_coop_status != hipSuccess) return g_coop_status;

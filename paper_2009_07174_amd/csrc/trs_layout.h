@@ -148,9 +148,10 @@ struct Pool {
   int32_t *front0, *front1; // frontier of the next round (round r appends to r&1)
   int32_t *ret0, *ret1;     // markers set in round r to retire in round r+1
   int32_t *qstamp;          // last notification stamp (deduplicates appends)
-  // plain mode: wake bits (bit p: an argument of the node became a normal
+  // plain mode: wake bits, two per slot (slot s: word s / 16, bit
+  // 2 (s mod 16) + p; bit p set: an argument of the node became a normal
   // form in a round of parity p since the node was last examined)
-  uint8_t *wake;
+  uint32_t *wake;
   // learned mode and tracing
   int32_t *lastchg;         // round in which the node was created or last changed
   int64_t *tref;            // tracing: record index << 32 | round of the

@@ -39,7 +39,8 @@ class trs_opts(ctypes.Structure):
                 ("max_rounds", ctypes.c_int64), ("threshold", ctypes.c_float),
                 ("persistent", ctypes.c_int32), ("trace", ctypes.c_int32),
                 ("trace_cap", ctypes.c_int64), ("label_horizon", ctypes.c_int32),
-                ("sweep_every", ctypes.c_int32), ("max_grid", ctypes.c_int32)]
+                ("sweep_every", ctypes.c_int32), ("max_grid", ctypes.c_int32),
+                ("pf_depth", ctypes.c_int32)]
 
 
 class trs_stats(ctypes.Structure):
@@ -86,13 +87,16 @@ class trs_tune_result(ctypes.Structure):
     _fields_ = [("trials", ctypes.c_int32), ("best_block", ctypes.c_int32),
                 ("best_npt", ctypes.c_int32), ("pad", ctypes.c_int32),
                 ("best_ms", ctypes.c_double), ("block", ctypes.c_int32 * 8),
-                ("npt", ctypes.c_int32 * 8), ("ms", ctypes.c_double * 8)]
+                ("npt", ctypes.c_int32 * 8), ("ms", ctypes.c_double * 8),
+                ("best_grid", ctypes.c_int32), ("pad2", ctypes.c_int32),
+                ("grid", ctypes.c_int32 * 8)]
 
     def as_dict(self):
         k = self.trials
         return {"trials": k, "best_block": self.best_block, "best_npt": self.best_npt,
-                "best_ms": self.best_ms,
-                "table": [(self.block[i], self.npt[i], self.ms[i]) for i in range(k)]}
+                "best_grid": self.best_grid, "best_ms": self.best_ms,
+                "table": [(self.block[i], self.npt[i], self.grid[i], self.ms[i])
+                          for i in range(k)]}
 
 
 TRS_MLP_EMB, TRS_MLP_DIN, TRS_MLP_H, TRS_MLP_MAX_SYM = 16, 24, 32, 256
@@ -356,12 +360,13 @@ class Options:
     label_horizon: int = 0
     sweep_every: int = 0
     max_grid: int = 0
+    pf_depth: int = 0
 
     def to_c(self) -> trs_opts:
         o = trs_default_opts()
         for k in ("mode", "block", "nodes_per_thread", "rounds_per_poll", "max_rounds",
                   "threshold", "persistent", "trace", "trace_cap", "label_horizon",
-                  "sweep_every", "max_grid"):
+                  "sweep_every", "max_grid", "pf_depth"):
             setattr(o, k, getattr(self, k))
         return o
 
@@ -461,4 +466,5 @@ class Context:
         best, res = trs_autotune(self.h, o.to_c())
         out = Options(**{k: getattr(o, k) for k in o.__dataclass_fields__})
         out.block, out.nodes_per_thread = best.block, best.nodes_per_thread
+        out.max_grid = best.max_grid
         return out, res

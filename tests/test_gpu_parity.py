@@ -194,6 +194,26 @@ def test_repeat_normalize_same_context():
         ctx.close()
 
 
+def test_autotune_plain_tunes_the_grid():
+    from paper_2009_07174_amd import trs as T
+    w = G.cfg3(60, 1 << 20, "mini")
+    ctx = T.Context(w.pool_slots, w.maxarity)
+    try:
+        ctx.load_trs(w.trs)
+        ctx.load_term_list(w.terms)
+        best, res = ctx.autotune(T.Options(mode=0))
+        say(f"[autotune plain] {res}")
+        assert res["trials"] == 4
+        assert all(npt == 16 and g > 0 for _, npt, g, _ in res["table"])
+        assert (best.block, best.max_grid) == (res["best_block"], res["best_grid"])
+        ctx.normalize(best)
+        nfs = [ctx.read_nf(i) for i in range(len(w.terms))]
+    finally:
+        ctx.close()
+    onfs, _ = run_oracle(w.trs, w.terms)
+    assert all(np.array_equal(a, b) for a, b in zip(nfs, onfs))
+
+
 def test_autotune_picks_a_shape_and_keeps_results():
     from paper_2009_07174_amd import trs as T
     w = G.cfg3(120, 1 << 21, "mini")
@@ -205,7 +225,7 @@ def test_autotune_picks_a_shape_and_keeps_results():
         say(f"[autotune] {res}")
         assert res["trials"] == 6
         assert (best.block, best.nodes_per_thread) == (res["best_block"], res["best_npt"])
-        assert res["best_ms"] == min(ms for _, _, ms in res["table"])
+        assert res["best_ms"] == min(ms for _, _, _, ms in res["table"])
         best2, res2 = ctx.autotune(T.Options(mode=1))   # cached
         assert res2["trials"] == 0 and best2.block == best.block
         ctx.normalize(best)
