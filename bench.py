@@ -319,6 +319,18 @@ def main():
                 "roofline_frac": algorithmic_bytes(sm, A)["total"] / wm / 1e9 / HBM_PEAK_GBPS,
                 "block": o.block, "nodes_per_thread": o.nodes_per_thread,
                 "max_grid": o.max_grid, "us_per_round": 1e6 * wm / max(sm["rounds"], 1)}
+            if m == "plain":
+                # the full-sweep round (the paper's method), per launch of the
+                # round kernel over the library's device time
+                abm = algorithmic_bytes(sm, A)["total"]
+                dev_s = sm["device_ms"] * 1e-3
+                res["roofline_full_sweep"] = {
+                    "bound": "hbm", "achieved": abm / dev_s / 1e9, "peak": HBM_PEAK_GBPS,
+                    "unit": "GB/s", "frac": abm / dev_s / 1e9 / HBM_PEAK_GBPS,
+                    "traffic": measured_traffic(w.name, "plain", o.block, o.nodes_per_thread),
+                    "kernel": "k_round", "mode": "plain", "launches_per_step": sm["launches"],
+                    "bytes_per_launch": abm / max(sm["launches"], 1),
+                    "avg_launch_us": 1e6 * dev_s / max(sm["launches"], 1)}
     if compare:
         # speedups over the plain sweep (the paper's method), from the time
         # of one normalisation in each mode

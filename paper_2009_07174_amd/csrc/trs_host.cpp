@@ -1173,6 +1173,8 @@ trs_status trs_autotune(trs_ctx *c, const trs_opts *base, trs_opts *best, trs_tu
   if (base->mode == TRS_MODE_PLAIN) {
     // full sweeps every round: wide workgroups (16 waves) with a grid of
     // about one or two per compute unit keep the most sweep tiles in flight
+    const trs_status ds = device_init(c);  // (the compute-unit count)
+    if (ds != TRS_OK) return ds;
     const int cu = std::max(1, c->cu_count);
     const int shapes[4][2] = {{1024, cu}, {512, cu}, {256, 2 * cu}, {1024, 2 * cu}};
     for (const auto &sh : shapes) {

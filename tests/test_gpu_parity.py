@@ -204,7 +204,8 @@ def test_autotune_plain_tunes_the_grid():
         best, res = ctx.autotune(T.Options(mode=0))
         say(f"[autotune plain] {res}")
         assert res["trials"] == 4
-        assert all(npt == 16 and g > 0 for _, npt, g, _ in res["table"])
+        # grids of one or two workgroups per compute unit (MI355X: 256 CUs)
+        assert all(npt == 16 and g >= 64 for _, npt, g, _ in res["table"])
         assert (best.block, best.max_grid) == (res["best_block"], res["best_grid"])
         ctx.normalize(best)
         nfs = [ctx.read_nf(i) for i in range(len(w.terms))]
