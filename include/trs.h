@@ -119,7 +119,8 @@ typedef struct {
                                 workgroups in frontier rounds */
   int32_t pf_depth;          /* with 16 nodes per thread: most sweep tiles a
                                 workgroup copies ahead into LDS (1..4; 0 = as
-                                many as fit, at most 4) */
+                                many as fit, at most 4; -1 = none, each tile
+                                read straight into registers) */
 } trs_opts;
 
 typedef struct {

@@ -76,7 +76,7 @@ struct trs_ctx {
   // captured chunk of rounds (one launch per round)
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
-  int g_grid = 0, g_block = 0, g_k = 0;
+  int g_grid = 0, g_block = 0, g_k = 0, g_sgrid = 0;
   size_t g_lds = 0;
   RoundArgs g_args;  // kernel arguments baked into the captured chunk
 
@@ -704,7 +704,7 @@ trs_status trs_normalize(trs_ctx *c, const trs_opts *opts_in, trs_stats *stats) 
   if (o.trace < 0 || o.trace > 65536) return c->fail(TRS_E_ARG, "trace rate must be 0..65536");
   if (o.max_grid < 0 || o.max_grid > (1 << 20))
     return c->fail(TRS_E_ARG, "max_grid must be 0..2^20");
-  if (o.pf_depth < 0 || o.pf_depth > 4) return c->fail(TRS_E_ARG, "pf_depth must be 0..4");
+  if (o.pf_depth < -1 || o.pf_depth > 4) return c->fail(TRS_E_ARG, "pf_depth must be -1..4");
   if (o.label_horizon < 0 || o.sweep_every < -1)
     return c->fail(TRS_E_ARG, "label_horizon must be >= 0, sweep_every >= -1");
   if (o.trace && o.mode != TRS_MODE_PLAIN)
@@ -762,6 +762,7 @@ trs_status trs_normalize(trs_ctx *c, const trs_opts *opts_in, trs_stats *stats) 
     // free-stack sizes, list lengths and flags (all zero but need and n)
     c->h_ctl->pub[2] = c->h_ctl->next_need;
     c->h_ctl->pub[3] = (int32_t)M1;
+    c->h_ctl->pub[10] = c->stamp_base;
   }
   HIPCHK(c, hipMemcpyAsync(c->d_ctl, c->h_ctl, sizeof(Ctl), hipMemcpyHostToDevice, s));
   unsigned long long zero = 0;
@@ -888,7 +889,7 @@ trs_status trs_normalize(trs_ctx *c, const trs_opts *opts_in, trs_stats *stats) 
   // sweep copies tiles ahead into an LDS ring, as deep (up to 4) as fits
   ra.qbuf = B >= 512 ? 2 : 4;
   ra.pf_depth = 0;
-  if (npt == 16) {
+  if (npt == 16 && o.pf_depth >= 0) {
     const int want = o.pf_depth > 0 ? o.pf_depth : 4;
     for (int d = want; d >= 1; d--) {
       if (trs_round_lds_bytes(B, npt, ra.tab_words, c->n_rules, d, ra.qbuf) <= 160 * 1024) {
@@ -922,6 +923,22 @@ trs_status trs_normalize(trs_ctx *c, const trs_opts *opts_in, trs_stats *stats) 
   // many items (a few passes of the workgroup), continuing for up to
   // cont_rounds rounds inside one launch
   ra.small_cap = 4 * B;
+  // plain mode, opt-in (TRS_SCAN=1): large full rounds are classified by
+  // k_scan, launched before each round launch, and run as list rounds (not
+  // in the persistent form).  Measured slower than the sweep inside k_round
+  // on the 4096-term batch (7.9 s against 6.3 s): its one list append per
+  // wave with slots to examine contends on a single counter.
+  ra.use_scan = (o.mode == TRS_MODE_PLAIN && !o.persistent && ra.use_memo &&
+                 std::getenv("TRS_SCAN") != nullptr) ? 1 : 0;
+  ra.round_block = B;
+  // the scan grid: a workgroup per scan tile, at most 8 per compute unit
+  auto scan_grid_for = [&](int64_t n) {
+    const int64_t ts = (int64_t)SCAN_BLOCK * SCAN_NPT;
+    int64_t need = std::max<int64_t>(1, (n + ts - 1) / ts);
+    int64_t g = 1;
+    while (g < need) g <<= 1;
+    return (int)std::min<int64_t>(g, 8 * (int64_t)std::max(1, c->cu_count));
+  };
   ra.cont_rounds = o.max_rounds > 0 ? (int)std::min<int64_t>(o.max_rounds + 1, 4096) : 4096;
   HIPCHK(c, hipEventRecord(c->ev0, s));
   const size_t small = offsetof(Ctl, stat);  // control words and round counters
@@ -952,7 +969,9 @@ trs_status trs_normalize(trs_ctx *c, const trs_opts *opts_in, trs_stats *stats) 
         launches++;
       }
     } else {
-      if (!c->gexec || c->g_grid != g || c->g_block != B || c->g_k != K || c->g_lds != lds ||
+      const int sg = ra.use_scan ? scan_grid_for(n_est) : 0;
+      if (!c->gexec || c->g_grid != g || c->g_sgrid != sg || c->g_block != B || c->g_k != K ||
+          c->g_lds != lds ||
           std::memcmp(&c->g_args, &ra, sizeof(ra)) != 0) {
         if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
         if (c->graph) (void)hipGraphDestroy(c->graph);
@@ -960,7 +979,8 @@ trs_status trs_normalize(trs_ctx *c, const trs_opts *opts_in, trs_stats *stats) 
         c->graph = nullptr;
         HIPCHK(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
         for (int k = 0; k < K; k++) {
-          hipError_t e = trs_launch_round(A, ra, g, B, s);
+          hipError_t e = ra.use_scan ? trs_launch_scan(A, ra, sg, s) : hipSuccess;
+          if (e == hipSuccess) e = trs_launch_round(A, ra, g, B, s);
           if (e != hipSuccess) {
             hipGraph_t junk;
             (void)hipStreamEndCapture(s, &junk);
@@ -970,6 +990,7 @@ trs_status trs_normalize(trs_ctx *c, const trs_opts *opts_in, trs_stats *stats) 
         HIPCHK(c, hipStreamEndCapture(s, &c->graph));
         HIPCHK(c, hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
         c->g_grid = g;
+        c->g_sgrid = sg;
         c->g_block = B;
         c->g_k = K;
         c->g_lds = lds;
@@ -1062,14 +1083,14 @@ trs_status trs_normalize(trs_ctx *c, const trs_opts *opts_in, trs_stats *stats) 
   }
   for (int i = 0; i < c->n_rules; i++) {
     unsigned long long t = 0;
-    for (int j = 0; j < 4; j++) t += h.rule_apps[i][j];
+    for (int j = 0; j < RULE_SPREAD; j++) t += h.rule_apps[j][i];
     c->rule_counts[i] = (int64_t)t;
   }
   if (stats) {
     std::memset(stats, 0, sizeof(*stats));
     auto sum = [&](int k) {
       unsigned long long t = 0;
-      for (int j = 0; j < CTL_SPREAD; j++) t += h.stat[k][j];
+      for (int j = 0; j < CTL_SPREAD; j++) t += h.stat[j][k];
       return (int64_t)t;
     };
     stats->rounds = h.done ? h.done_round : r;

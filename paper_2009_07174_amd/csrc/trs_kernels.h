@@ -23,6 +23,9 @@ struct RoundArgs {
                         // 2 frontier chosen by the predictor (full sweep when
                         // the frontier is empty)
   int32_t use_memo;     // memo shortcut on (off in learned mode and tracing)
+  int32_t use_scan;     // plain mode: large full rounds are classified by k_scan
+                        // (launched before each k_round) and run as list rounds
+  int32_t round_block;  // k_round's block size (for the scan's hand-over)
   int32_t gate_off;     // learned mode: word offset of the decision table in tab
   uint32_t trace_rate;  // tracing: keep a blocked node-round when its hash
                         // (16 bits) is below this; 0 = off
@@ -51,9 +54,17 @@ struct RoundArgs {
 // work passes done.
 #define TRACE_FIELDS 16
 
+// Threads per workgroup of k_scan, and slots per thread per tile.
+#define SCAN_BLOCK 256
+#define SCAN_NPT 16
+
 // LDS bytes a round kernel needs for this configuration.
 size_t trs_round_lds_bytes(int block, int npt, int tab_words, int n_rules, int pf_depth,
                            int qbuf);
+
+// Launches the plain-mode scan (k_scan) on stream s; it does nothing unless
+// the published round state requests a scan.
+hipError_t trs_launch_scan(int A, const RoundArgs &a, int grid, hipStream_t s);
 
 // Sets kernel attributes (dynamic LDS above 64 KiB); call before launching
 // or capturing with a given LDS size.

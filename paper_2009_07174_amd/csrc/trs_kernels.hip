@@ -68,6 +68,40 @@ __device__ __forceinline__ void st(int32_t *p, int v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// End-of-launch ticket (thread 0 of each of the gt workgroups that take
+// one): true for the workgroup that finishes last.  Two levels: a counter
+// per group of workgroups (wg mod ng), then one for the groups, with ng about
+// the square root of gt, so no counter takes more than about 2 sqrt(gt)
+// same-address atomics.  Each counter is reset by the one that completes
+// it.  flags (bit 0: met a live non-normal-form slot, bit 1: made progress)
+// travel up with the tickets; the last workgroup gets in *flags whether any
+// workgroup set each.  The caller has waited for its own memory operations
+// first.
+__device__ __forceinline__ bool last_ticket(Ctl *ctl, int wg, int gt, int *flags) {
+  int ng = 1;
+  while (ng * ng < gt && ng < TICKET_GROUPS) ng <<= 1;
+  const int g = wg & (ng - 1);
+  const int gsize = (gt - g + ng - 1) / ng;  // workgroups w < gt with w mod ng = g
+  auto enc = [](int f) {
+    return 1ull | ((unsigned long long)(f & 1) << 32) | ((unsigned long long)((f >> 1) & 1) << 48);
+  };
+  auto dec = [](unsigned long long v) {
+    return (((v >> 32) & 0xffff) ? 1 : 0) | ((v >> 48) ? 2 : 0);
+  };
+  unsigned long long *c1 = &ctl->tickets[g][0];
+  const unsigned long long a1 = enc(*flags);
+  const unsigned long long v1 = atomicAdd(c1, a1) + a1;
+  if ((int)(v1 & 0xffffffffu) != gsize) return false;
+  __hip_atomic_store(c1, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  unsigned long long *c2 = &ctl->tickets[TICKET_GROUPS][0];
+  const unsigned long long a2 = enc(dec(v1));
+  const unsigned long long v2 = atomicAdd(c2, a2) + a2;
+  if ((int)(v2 & 0xffffffffu) != min(ng, gt)) return false;
+  __hip_atomic_store(c2, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  *flags = dec(v2);
+  return true;
+}
+
 // Workgroup barrier for LDS traffic only: each wave waits for its own LDS
 // operations, not for its global stores and atomics.  Within a round no wave
 // reads what another wave of its workgroup wrote to global memory (the
@@ -877,9 +911,20 @@ __device__ __forceinline__ int collect(const RoundArgs &a, const Lds &L, RoundCn
 }
 
 // State of round r, derived from the counters of round r-1.
+// published flags (pub[9], besides err << 8)
+#define PUB_STOP 1
+#define PUB_QUIESCENT 2
+#define PUB_STALL 4
+#define PUB_SCANNED 8    // the round's slots were classified by k_scan
+#define PUB_SCAN_REQ 16  // the round is a plain full sweep for k_scan
+
 struct RoundState {
   int r, n, fs0, fs1, nd, nfront, nret, nlist, ntiles, need, err;
+  int stamp;  // first frontier-notification stamp of the run
   bool stop, quiescent, full, done;
+  bool scan_req;  // plain mode: a full round large enough for k_scan
+  bool scanned;   // k_scan classified the round's slots: a list round of the
+                  // dead nodes and the listed slots
   bool stall;  // the previous round met live non-normal-form slots but made no
                // progress: this round is a full sweep that tests every slot
                // (plain mode: ignoring the wake bits)
@@ -960,6 +1005,8 @@ __device__ __forceinline__ RoundState round_state(const RoundArgs &a, int r) {
   rs.need = max((rs.nlist + B - 1) / B, rs.ntiles);
   if (rs.ntiles <= 1 && rs.nlist <= a.small_cap) rs.need = 1;
   if (stop) rs.need = 1;
+  rs.scanned = false;
+  rs.scan_req = a.use_scan && a.mode == 0 && rs.full && !stall && !stop && rs.ntiles >= 2;
   return rs;
 }
 
@@ -993,6 +1040,7 @@ __device__ __forceinline__ RoundState round_prepare(const RoundArgs &a, const Ld
       bc[7] = y.w;
       bc[8] = z.x;
       bc[9] = z.y;
+      L.misc[29] = z.z;  // the run's stamp base, kept for the whole launch
     } else {
       const RoundState t = round_state(a, r);
       bc[0] = 0;
@@ -1004,7 +1052,8 @@ __device__ __forceinline__ RoundState round_prepare(const RoundArgs &a, const Ld
       bc[6] = t.nd;
       bc[7] = t.nfront;
       bc[8] = t.nret;
-      bc[9] = (t.stop ? 1 : 0) | (t.quiescent ? 2 : 0) | (t.stall ? 4 : 0) | (t.err << 8);
+      bc[9] = (t.stop ? PUB_STOP : 0) | (t.quiescent ? PUB_QUIESCENT : 0) |
+              (t.stall ? PUB_STALL : 0) | (t.err << 8);
     }
   }
   lds_sync();
@@ -1018,14 +1067,20 @@ __device__ __forceinline__ RoundState round_prepare(const RoundArgs &a, const Ld
   rs.nd = bc[6];
   rs.nfront = bc[7];
   rs.nret = bc[8];
-  rs.stop = bc[9] & 1;
-  rs.quiescent = bc[9] & 2;
-  rs.stall = bc[9] & 4;
+  rs.stop = bc[9] & PUB_STOP;
+  rs.quiescent = bc[9] & PUB_QUIESCENT;
+  rs.stall = bc[9] & PUB_STALL;
+  rs.scanned = bc[9] & PUB_SCANNED;
+  rs.scan_req = false;
   rs.err = bc[9] >> 8;
+  rs.stamp = L.misc[29];
   lds_sync();
   tmark(a, L, rs.r, 0);
-  rs.full = !rs.quiescent && (a.mode == 0 || rs.nfront == 0 || rs.r == 0 || rs.stall ||
-                              (a.sweep_every > 0 && rs.r % a.sweep_every == 0));
+  // a scanned round is a list round: the scan listed the slots to examine
+  // (nfront of them) and retired the markers
+  rs.full = !rs.quiescent && !rs.scanned &&
+            (a.mode == 0 || rs.nfront == 0 || rs.r == 0 || rs.stall ||
+             (a.sweep_every > 0 && rs.r % a.sweep_every == 0));
   rs.nlist = rs.nd + (rs.full ? 0 : rs.nret + rs.nfront);
   rs.ntiles = rs.full ? (rs.n + B * a.npt - 1) / (B * a.npt) : 0;
   rs.need = max((rs.nlist + B - 1) / B, rs.ntiles);
@@ -1038,7 +1093,8 @@ __device__ __forceinline__ RoundState round_prepare(const RoundArgs &a, const Ld
 __device__ __forceinline__ void publish(Ctl *ctl, const RoundState &nx) {
   const int v[10] = {0,         nx.r,      nx.need,   nx.n,      nx.fs0,
                      nx.fs1,    nx.nd,     nx.nfront, nx.nret,
-                     (nx.stop ? 1 : 0) | (nx.quiescent ? 2 : 0) | (nx.stall ? 4 : 0) |
+                     (nx.stop ? PUB_STOP : 0) | (nx.quiescent ? PUB_QUIESCENT : 0) |
+                         (nx.stall ? PUB_STALL : 0) | (nx.scan_req ? PUB_SCAN_REQ : 0) |
                          (nx.err << 8)};
 #pragma unroll
   for (int i = 0; i < 10; i++)
@@ -1077,13 +1133,14 @@ __device__ __forceinline__ void round_execute(const RoundArgs &a, Lds &L, const 
     st(&ctl->fs[r3][1], fs1);
     RoundCnt *nx = &ctl->cnt[(r + 1) % 3];
     for (int32_t *w : {&nx->alloc, &nx->push, &nx->dead, &nx->active, &nx->err, &nx->front,
-                       &nx->ret, &nx->full, &nx->prog})
+                       &nx->ret, &nx->full, &nx->prog, &nx->scan})
       st(w, 0);
-    st(&ctl->cnt[r3].full, (full || quiescent) ? 1 : 0);
+    // (a scanned round examined every slot; the scan counted its visits)
+    st(&ctl->cnt[r3].full, (full || quiescent || rs.scanned) ? 1 : 0);
     if ((unsigned long long)n > L.lstat[LSTAT_PEAK]) L.lstat[LSTAT_PEAK] = n;
     if (nd > 0) L.lstat[LSTAT_GC]++;
     if (full) L.lstat[LSTAT_FULL]++;
-    L.lstat[STAT_VISITS] += (unsigned long long)(full ? n : nfront);
+    if (!rs.scanned) L.lstat[STAT_VISITS] += (unsigned long long)(full ? n : nfront);
   }
   // the first `need` workgroups run the round; list items and tiles are
   // strided over exactly those
@@ -1096,7 +1153,7 @@ __device__ __forceinline__ void round_execute(const RoundArgs &a, Lds &L, const 
   R.e = (unsigned)(r & 1);
   R.mode = mode;
   R.cnt = cnt;
-  R.stamp = ld(&ctl->stamp_base) + r;
+  R.stamp = rs.stamp + r;
   R.SP = (r & 1) ? p.fstack1 : p.fstack0;
   R.fsP = (r & 1) ? fs1 : fs0;
   int32_t *SQ = ((r + 1) & 1) ? p.fstack1 : p.fstack0;
@@ -1113,10 +1170,16 @@ __device__ __forceinline__ void round_execute(const RoundArgs &a, Lds &L, const 
   const unsigned ep = (unsigned)((r - 1) & 1);
 
   tmark(a, L, r, 2);
-  // ---- 1. list items: collection, marker retirement, frontier slots
+  // ---- 1. list items: collection, marker retirement, frontier slots.  In
+  // a full round the list holds only the dead nodes, and their collection
+  // is deferred to the sweep's last passes, where it runs beside the
+  // examination of the swept slots (one dependent chain instead of two; the
+  // order of the two within a round does not matter, since dead nodes are
+  // normal forms, which the sweep never examines)
+  const bool defer_dead = full && ntiles > 0;
   {
     const int nr_here = full ? 0 : nret;
-    for (int base = wg * B; base < nlist; base += Ga * B) {
+    for (int base = wg * B; base < (defer_dead ? 0 : nlist); base += Ga * B) {
       const int i = base + tid;
       int s = 0, memo = 0, fslot = 0;
       Pre<A> pre;
@@ -1150,7 +1213,8 @@ __device__ __forceinline__ void round_execute(const RoundArgs &a, Lds &L, const 
           }
         }
       }
-      process_slot<A>(a, L, R, s, memo, false, fslot, SQ, fsQ, C, pre);
+      // (a scanned round's listed slots were counted as live by the scan)
+      process_slot<A>(a, L, R, s, memo, rs.scanned, fslot, SQ, fsQ, C, pre);
     }
   }
 
@@ -1187,6 +1251,9 @@ __device__ __forceinline__ void round_execute(const RoundArgs &a, Lds &L, const 
         if (t + k * Ga < ntiles) pf_issue(t + k * Ga, k);
     }
     int Wb = 0;  // work-list items carried over from earlier tiles
+    // deferred dead-list items of this workgroup: dbase, dbase + Ga B, ...
+    const int nd_def = defer_dead ? nd : 0;
+    int dbase = wg * B;
     for (int it = 0; t < ntiles; t += Ga, it++) {
       const int b_cur = ahead ? it % depth : 0;  // ring buffer of this tile
       // (phase trace: fields 1 and 12-15 time the third tile of the sweep, in
@@ -1339,15 +1406,20 @@ __device__ __forceinline__ void round_execute(const RoundArgs &a, Lds &L, const 
       // rest carries over to the next tile (the list holds a tile plus B),
       // and after the last tile everything is examined
       const bool last = t + Ga >= ntiles;
-      while (W >= B || (last && W > 0)) {
+      while (W >= B || (last && (W > 0 || dbase < nd_def))) {
         // (process_slot's barriers order these reads before later appends
         // over the same entries)
         const int take = min(W, B);
         const int wv = tid < take ? L.work[W - take + tid] : 0;
+        int fslot = 0;
+        if (last && dbase < nd_def) {  // deferred collection, beside the last passes
+          if (dbase + tid < nd_def) fslot = collect<A>(a, L, cnt, D[dbase + tid], C);
+          dbase += Ga * B;
+        }
         Pre<A> none;
         none.have = false;
-        process_slot<A>(a, L, R, wv & 0x1fffffff, (int)((unsigned)wv >> 29), true, 0, SQ, fsQ,
-                        C, none);
+        process_slot<A>(a, L, R, wv & 0x1fffffff, (int)((unsigned)wv >> 29), true, fslot, SQ,
+                        fsQ, C, none);
         W -= take;
       }
       Wb = W;
@@ -1357,6 +1429,15 @@ __device__ __forceinline__ void round_execute(const RoundArgs &a, Lds &L, const 
       // two or more buffers: the tile depth strides ahead goes into the one
       // just read, as the iteration's last memory operation
       if (depth >= 2 && t + depth * Ga < ntiles) pf_issue(t + depth * Ga, b_cur);
+    }
+    // a workgroup without tiles still collects its share of the dead list
+    while (dbase < nd_def) {
+      int fslot = 0;
+      if (dbase + tid < nd_def) fslot = collect<A>(a, L, cnt, D[dbase + tid], C);
+      dbase += Ga * B;
+      Pre<A> none;
+      none.have = false;
+      process_slot<A>(a, L, R, 0, 0, true, fslot, SQ, fsQ, C, none);
     }
   }
 
@@ -1393,13 +1474,15 @@ __device__ __forceinline__ void round_execute(const RoundArgs &a, Lds &L, const 
     }
   }
   lds_sync();
-  if (tid == 0 && L.misc[32]) {
-    st(&cnt->active, 1);
-    L.misc[32] = 0;
-  }
-  if (tid == 0 && L.misc[33]) {
-    st(&cnt->prog, 1);
-    L.misc[33] = 0;
+  // the round's two flags: stored here by a workgroup running the round
+  // alone (it may go on to the next round itself) and in the persistent
+  // form (nrounds > 0: no tickets); otherwise they travel with the
+  // end-of-launch tickets (a store per workgroup to one address would
+  // serialise)
+  if (tid == 0 && (Ga == 1 || a.nrounds > 0)) {
+    if (L.misc[32]) st(&cnt->active, 1);
+    if (L.misc[33]) st(&cnt->prog, 1);
+    L.misc[32] = L.misc[33] = 0;
   }
   if (tid == 0) L.misc[24] = L.misc[25] = L.misc[26] = 0;  // the sweep's tile counters
   // end of the round: every wave's global writes complete before the
@@ -1419,7 +1502,7 @@ __device__ __forceinline__ void flush_stats(const RoundArgs &a, const Lds &L) {
   if (tid == 0) {
     const int sp = wg & (CTL_SPREAD - 1);
     for (int k = 0; k < CTL_NSTAT; k++)
-      if (L.lstat[k]) atomicAdd(&ctl->stat[k][sp], L.lstat[k]);
+      if (L.lstat[k]) atomicAdd(&ctl->stat[sp][k], L.lstat[k]);
     if (L.lstat[LSTAT_GC]) atomicAdd((unsigned *)&ctl->gc_rounds, (unsigned)L.lstat[LSTAT_GC]);
     if (L.lstat[LSTAT_FULL])
       atomicAdd((unsigned *)&ctl->full_sweeps, (unsigned)L.lstat[LSTAT_FULL]);
@@ -1427,7 +1510,7 @@ __device__ __forceinline__ void flush_stats(const RoundArgs &a, const Lds &L) {
   }
   for (int i = tid; i < a.n_rules; i += blockDim.x) {
     const int c = L.rcnt[i];
-    if (c) atomicAdd(&ctl->rule_apps[i][wg & 3], (unsigned long long)c);
+    if (c) atomicAdd(&ctl->rule_apps[wg & (RULE_SPREAD - 1)][i], (unsigned long long)c);
   }
 }
 
@@ -1486,7 +1569,8 @@ __global__ void __launch_bounds__(1024) k_round(RoundArgs a) {
   // without a ticket, so a launch costs as many control atomics as
   // workgroups at work, however large its grid.
   RoundState rs = round_prepare(a, L, 0, true, true);
-  int r_exec = rs.r;  // the last round this workgroup executed (phase trace)
+  const int r0 = rs.r;  // the launch's first round
+  int r_exec = rs.r;    // the last round this workgroup executed (phase trace)
   if (rs.done) return;
   const int need0 = rs.need;
   if (wg >= need0) return;
@@ -1529,8 +1613,14 @@ __global__ void __launch_bounds__(1024) k_round(RoundArgs a) {
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (tid == 0) {
-    const int t = atomicAdd(&ctl->ticket, 1);
-    if (t == min(need0, (int)gridDim.x) - 1) {
+    int flags = (L.misc[32] ? 1 : 0) | (L.misc[33] ? 2 : 0);  // (set only by rounds run by more
+                                                               // than one workgroup)
+    if (last_ticket(ctl, wg, min(need0, (int)gridDim.x), &flags)) {
+      if (flags) {
+        RoundCnt *c0 = &ctl->cnt[r0 % 3];
+        if (flags & 1) st(&c0->active, 1);
+        if (flags & 2) st(&c0->prog, 1);
+      }
       // last working workgroup of the launch: every round it covered is
       // complete.  It reads only counters kept with agent-scope atomics, so
       // it needs no fence either.
@@ -1542,7 +1632,6 @@ __global__ void __launch_bounds__(1024) k_round(RoundArgs a) {
       else
         tmark_any(a, rr - 1, 11);
       __hip_atomic_store(&ctl->next_need, nx.need, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&ctl->ticket, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_store(&ctl->r_cur, rr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     tflush(a, L, r_exec);
@@ -1581,6 +1670,132 @@ __device__ __forceinline__ bool grid_barrier(unsigned long long *bar, unsigned l
   return *lds_flag == 0;
 }
 
+// Plain mode, a large full round r: the classification of every slot below n
+// that k_round's sweep would make, as a kernel of its own.  Markers of the
+// previous round are retired, woken sleepers' wake bits cleared, and the
+// slots to examine listed in the frontier buffer of parity (r-1)&1 (count in
+// cnt[r%3].scan; one fetch-add per wave).  The last workgroup turns the
+// published round into a list round of the dead nodes and the listed slots,
+// which the k_round launch that follows examines.  There is no work list in
+// LDS, no barrier per tile and no rewrite code here, so the kernel holds
+// few registers and many waves stream the state bytes; it does nothing
+// unless the round was published with a scan request.
+template <int A>
+__global__ void __launch_bounds__(SCAN_BLOCK) k_scan(RoundArgs a) {
+  Ctl *ctl = a.ctl;
+  const Pool &p = a.p;
+  __shared__ unsigned long long s_act, s_still;
+  const int tid = threadIdx.x;
+  const int4 *pp = reinterpret_cast<const int4 *>(ctl->pub);
+  const int4 x = pp[0], y = pp[1], z = pp[2];  // done r need n | fs0 fs1 nd nfront | nret flags
+  if (x.x != 0) return;
+  const int flags = z.y;
+  if (!(flags & PUB_SCAN_REQ) || (flags & (PUB_SCANNED | PUB_STOP))) return;
+  const int r = x.y, n = x.w, nd = y.z, nret = z.x;
+  const unsigned e = (unsigned)(r & 1);
+  int32_t *X = ((r - 1) & 1) ? p.front1 : p.front0;
+  RoundCnt *cnt = &ctl->cnt[r % 3];
+  if (tid == 0) {
+    s_act = 0;
+    s_still = 0;
+  }
+  __syncthreads();
+  constexpr int TS = SCAN_BLOCK * SCAN_NPT;
+  const int ntiles = (n + TS - 1) / TS;
+  int act = 0, still_n = 0;
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int base = t * TS + tid * SCAN_NPT;
+    const uint4 vs = *reinterpret_cast<const uint4 *>(p.state + base);
+    const unsigned ww = p.wake[base >> 4];
+    int valid = 0xffff;
+    if (base == 0) valid &= ~1;
+    {
+      const int lim = n - base;
+      if (lim < SCAN_NPT) valid &= lim > 0 ? (1 << lim) - 1 : 0;
+    }
+    int pending = 0, memoed = 0, retire = 0;
+    {
+      const unsigned er = e ? 0x01010101u : 0u;
+      const unsigned w4[4] = {vs.x, vs.y, vs.z, vs.w};
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        const unsigned xw = w4[q];
+        const unsigned pend = (xw >> 1) & 0x01010101u;
+        const unsigned prev = pend & (((xw >> 2) & 0x01010101u) ^ er);
+        const unsigned nf = (xw >> 7) & 0x01010101u;
+        const unsigned live = ((xw & 0x7f7f7f7fu) + 0x7f7f7f7fu) >> 7;
+        const unsigned normal = live & ~pend;
+        const unsigned mem = ((xw & 0x38383838u) + 0x78787878u) >> 7;
+        pending |= pack4(normal | (prev & ~nf)) << (4 * q);
+        memoed |= pack4(normal & mem) << (4 * q);
+        retire |= pack4(prev) << (4 * q);
+      }
+    }
+    pending &= valid;
+    memoed &= valid;
+    retire &= valid;
+    for (int m = retire; m; m &= m - 1) {
+      const int j = __builtin_ctz(m);
+      const unsigned stb = (((j >> 2) == 0 ? vs.x : (j >> 2) == 1 ? vs.y : (j >> 2) == 2 ? vs.z : vs.w)
+                            >> ((j & 3) * 8)) & 0xffu;
+      p.state[base + j] = (uint8_t)((stb & ST_NF) ? ST_NF : ST_ACTIVE);
+    }
+    const int wmask = even_bits(ww >> (1u - e));
+    const int still = memoed & ~wmask;
+    for (int m = memoed & wmask; m; m &= m - 1) {
+      const int slot = base + __builtin_ctz(m);
+      atomicAnd(&p.wake[slot >> 4], ~(1u << (((slot & 15) << 1) | (1u - e))));
+    }
+    act += __popc(pending);
+    still_n += __popc(still);
+    const int exam = pending & ~still;
+    if (__ballot(exam != 0)) {
+      const int c = __popc(exam);
+      const int incl = wave_incl_scan(c);
+      const int tot = __shfl(incl, 63, 64);
+      int wb = 0;
+      if (lane() == 63) wb = atomicAdd(&cnt->scan, tot);
+      int pos = __shfl(wb, 63, 64) + incl - c;
+      for (int m = exam; m; m &= m - 1) X[pos++] = base + __builtin_ctz(m);
+    }
+  }
+  {
+    const int sa = wave_sum(act), ss = wave_sum(still_n);
+    if (lane() == 0) {
+      if (sa) atomicAdd(&s_act, (unsigned long long)sa);
+      if (ss) atomicAdd(&s_still, (unsigned long long)ss);
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    const int sp = blockIdx.x & (CTL_SPREAD - 1);
+    if (s_act) atomicAdd(&ctl->stat[sp][STAT_ACTIVE], s_act);
+    if (s_still) atomicAdd(&ctl->stat[sp][STAT_MEMO], s_still);
+    if (blockIdx.x == 0) {
+      atomicAdd(&ctl->stat[sp][STAT_VISITS], (unsigned long long)n);
+      atomicAdd((unsigned *)&ctl->full_sweeps, 1u);
+    }
+  }
+  // as in k_round: each wave's fetch-adds complete before the ticket
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (tid == 0) {
+    int fl = s_act ? 1 : 0;
+    if (last_ticket(ctl, blockIdx.x, gridDim.x, &fl)) {
+      if (fl & 1) st(&cnt->active, 1);
+      const int nx = ld(&cnt->scan);
+      const int nlist = nd + nret + nx;
+      const int B = a.round_block;
+      int need = max(1, (nlist + B - 1) / B);
+      if (nlist <= a.small_cap) need = 1;
+      st(&ctl->pub[2], need);
+      st(&ctl->pub[7], nx);
+      st(&ctl->pub[9], (flags & ~PUB_SCAN_REQ) | PUB_SCANNED);
+      st(&ctl->next_need, need);
+    }
+  }
+}
+
 template <int A>
 __global__ void __launch_bounds__(1024) k_persistent(RoundArgs a) {
   extern __shared__ int32_t smem[];
@@ -1588,6 +1803,7 @@ __global__ void __launch_bounds__(1024) k_persistent(RoundArgs a) {
   if (ld(&ctl->done) || ld(&ctl->abort)) return;
   Lds L = setup_lds(a, smem, true);
   const unsigned long long G = gridDim.x;
+  if (threadIdx.x == 0) L.misc[29] = ld(&ctl->stamp_base);  // (read by round_prepare)
   const int r0 = bcast(L, threadIdx.x == 0 ? ld(&ctl->r_cur) : 0);
   int r = r0;
   for (int k = 0; k < a.nrounds; k++, r++) {
@@ -1663,6 +1879,16 @@ static void set_attr_A(size_t lds) {
 hipError_t trs_prepare_kernels(int A, size_t lds) {
   if (lds > 65536) DISPATCH_A(A, set_attr_A, lds);
   return hipSuccess;
+}
+
+template <int A>
+static void launch_scan_A(const RoundArgs &a, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_scan<A>, dim3(grid), dim3(SCAN_BLOCK), 0, s, a);
+}
+
+hipError_t trs_launch_scan(int A, const RoundArgs &a, int grid, hipStream_t s) {
+  DISPATCH_A(A, launch_scan_A, a, grid, s);
+  return hipGetLastError();
 }
 
 hipError_t trs_launch_round(int A, const RoundArgs &a, int grid, int block, hipStream_t s) {

@@ -81,6 +81,8 @@ static inline int32_t tab_sym_word(int32_t arity, int32_t nrules, int32_t first,
 
 // ---------------------------------------------------------------- control
 #define CTL_SPREAD 64    // statistics counters are spread over this many words
+#define RULE_SPREAD 16   // per-rule counters are spread over this many copies
+#define TICKET_GROUPS 64
 #define CTL_NSTAT 12
 enum {
   STAT_ACTIVE = 0,  // live non-normal-form slots visited
@@ -97,16 +99,30 @@ enum {
   STAT_TRACE,       // trace records logged (including ones past the cap)
 };
 
+// Each counter on a 128-byte line of its own: atomics to one line
+// serialise, and every workgroup of a launch updates several of them.
+#define RC_PAD(name) int32_t name##_pad[31]
 struct RoundCnt {
   int32_t alloc;   // allocation claims in the round
+  RC_PAD(alloc);
   int32_t push;    // free-stack pushes in the round
+  RC_PAD(push);
   int32_t dead;    // dead-list appends in the round
+  RC_PAD(dead);
   int32_t active;  // nonzero if a live non-normal-form slot was seen
+  RC_PAD(active);
   int32_t err;     // nonzero: trs_status of a device-detected error
+  RC_PAD(err);
   int32_t front;   // appends to the next round's frontier
+  RC_PAD(front);
   int32_t ret;     // appends to the retire list
+  RC_PAD(ret);
   int32_t full;    // the round examined every slot (full sweep)
+  RC_PAD(full);
   int32_t prog;    // a node fired or became a normal form in the round
+  RC_PAD(prog);
+  int32_t scan;    // plain mode: slots the round's scan listed for examination
+  RC_PAD(scan);
 };
 
 struct Ctl {
@@ -123,16 +139,28 @@ struct Ctl {
   int32_t abort;       // set when a device-wide barrier wait timed out
   int32_t stamp_base;  // frontier-notification stamps of this run start here
   int32_t full_sweeps; // rounds that swept every slot
-  int32_t ticket;      // workgroups of the current launch that have finished
   int32_t r_reached;   // round after the last one workgroup 0 ran alone
-  int32_t pad2[3];
-  RoundCnt cnt[3];     // counters accumulated during round r (index r % 3)
+  int32_t pad2[4];
+  alignas(128) RoundCnt cnt[3];  // counters accumulated during round r (index r % 3)
   // state of the next launch's first round, published by the last workgroup
   // of a launch (the host writes it for round 0): done, r, need, n, fs0, fs1,
-  // dead, frontier, retire, flags (stop | quiescent<<1 | stall<<2 | err<<8)
+  // dead, frontier, retire, flags (stop | quiescent<<1 | stall<<2 |
+  // scanned<<3 | scan requested<<4 | err<<8), and (set by the host, read
+  // with the rest) the run's first frontier-notification stamp
   alignas(64) int32_t pub[16];
-  unsigned long long stat[CTL_NSTAT][CTL_SPREAD];
-  unsigned long long rule_apps[256][4];
+  // statistics, spread-major: the counters of one workgroup share cache
+  // lines, those of workgroups with different wg mod CTL_SPREAD do not, so
+  // a launch's end-of-launch atomics contend little on any one line
+  unsigned long long stat[CTL_SPREAD][CTL_NSTAT];
+  unsigned long long rule_apps[RULE_SPREAD][256];
+  // end-of-launch tickets in two levels (a counter per group of workgroups,
+  // then one for the groups), each counter on a 128-byte line of its own:
+  // same-address atomics serialise, and a single counter cost about 50 ns
+  // per workgroup
+  // (64-bit: workgroups in bits 0-31, and the numbers of them that met a
+  // live non-normal-form slot (bits 32-47) and made progress (48-63), so
+  // the last one knows the round's two flags without a store per workgroup)
+  unsigned long long tickets[TICKET_GROUPS + 1][16];
 };
 
 struct Pool {
