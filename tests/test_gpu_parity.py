@@ -236,3 +236,27 @@ def test_autotune_picks_a_shape_and_keeps_results():
     onfs, _ = run_oracle(w.trs, w.terms)
     assert all(np.array_equal(a, b) for a, b in zip(nfs, onfs))
 
+
+
+@pytest.mark.parametrize("case", ["batch_mini", "cfg2", "fib20"])
+def test_plain_scan_kernel_agrees(case, monkeypatch):
+    """The opt-in plain-mode scan kernel (TRS_SCAN=1): a separate launch
+    classifies the slots of each large full round and the round kernel then
+    examines the listed slots; results and counts equal the oracle's, and
+    the statistics equal those of the sweep inside the round kernel."""
+    if case == "batch_mini":
+        w = G.cfg3(200, 1 << 22, "mini")
+        trs, terms, pool, A = w.trs, w.terms, w.pool_slots, w.maxarity
+    elif case == "cfg2":
+        trs = systems.msort()
+        vals = np.random.default_rng(G.BASE_SEED + 2).integers(0, 64, size=512)
+        terms, pool, A = [G.sort_term(trs, vals)], 1 << 22, 3
+    else:
+        trs = systems.fib()
+        terms, pool, A = [G.g_term(trs, 20)], 1 << 20, 2
+    opts = dict(mode=0, block=256, nodes_per_thread=16)
+    base = assert_parity(trs, terms, pool, A, label=f"plain sweep {case}", **opts)
+    monkeypatch.setenv("TRS_SCAN", "1")
+    scan = assert_parity(trs, terms, pool, A, label=f"plain scan {case}", **opts)
+    for k in ("rounds", "node_visits", "active_visits", "ready_visits", "full_sweeps", "memo_blocked"):
+        assert scan[k] == base[k], k
