@@ -186,13 +186,14 @@ int64_t trs_device_bytes(int64_t pool_slots, int32_t maxarity);
 /* Default options (mode plain, tuned block and nodes per thread). */
 void trs_default_opts(trs_opts *opts);
 
-/* Autotuner of the launch shape (the batching step: block size, nodes per
- * thread and, for the plain sweep, the grid).  Times complete trs_normalize
+/* Autotuner of the launch shape (the batching step: block size and nodes
+ * per thread; max_grid is part of the result).  Times complete trs_normalize
  * runs of the loaded terms under *base.  Frontier and learned modes: block
  * sizes 128, 256, 512, 1024 at 16 nodes per thread, then 4 and 8 nodes per
- * thread at the best block (six runs, default grid).  Plain mode, whose
- * rounds are full sweeps: (block, grid) in (1024, 256), (512, 256),
- * (256, 512), (1024, 512) at 16 nodes per thread (four runs).  *best
+ * thread at the best block (six runs, default grid).  Plain mode, whose large
+ * rounds are classified by the scan kernel and examined as lists: (block,
+ * nodes per thread) in (128, 16), (128, 8), (64, 16), (256, 16) (four
+ * runs).  *best
  * receives *base with the fastest block, nodes_per_thread and max_grid.  The
  * result is cached per context and loaded terms (a second call with the same
  * mode returns it without trials; res->trials = 0 then).  After the call the

@@ -923,21 +923,29 @@ trs_status trs_normalize(trs_ctx *c, const trs_opts *opts_in, trs_stats *stats) 
   // many items (a few passes of the workgroup), continuing for up to
   // cont_rounds rounds inside one launch
   ra.small_cap = 4 * B;
-  // plain mode, opt-in (TRS_SCAN=1): large full rounds are classified by
-  // k_scan, launched before each round launch, and run as list rounds (not
-  // in the persistent form).  Measured slower than the sweep inside k_round
-  // on the 4096-term batch (7.9 s against 6.3 s): its one list append per
-  // wave with slots to examine contends on a single counter.
+  // plain mode: large full rounds are classified by k_scan, launched before
+  // each round launch, and run as list rounds (not in the persistent form,
+  // nor when tracing; TRS_NO_SCAN=1 keeps the sweep inside k_round).  On the
+  // 4096-term batch: 5.4 s against 6.3 s for the in-kernel sweep.
   ra.use_scan = (o.mode == TRS_MODE_PLAIN && !o.persistent && ra.use_memo &&
-                 std::getenv("TRS_SCAN") != nullptr) ? 1 : 0;
+                 std::getenv("TRS_NO_SCAN") == nullptr) ? 1 : 0;
   ra.round_block = B;
-  // the scan grid: a workgroup per scan tile, at most 8 per compute unit
+  // the scan's lists: 16 (each of N/8 entries, 8 in each frontier buffer)
+  // for pools of 2^24 slots or more, whose lists then hold every slot a
+  // list's workgroups can list (at most n/16 + 2^19 + 2^10 for grids of at
+  // most 512); else one list of N entries
+  {
+    const int64_t N = c->cfg.pool_slots;
+    ra.scan_lists = N >= (int64_t)1 << 24 ? 16 : 1;
+    ra.scan_rs = ra.scan_lists == 16 ? N / 8 : N;
+  }
+  // the scan grid: a workgroup per scan tile, at most 2 per compute unit
   auto scan_grid_for = [&](int64_t n) {
     const int64_t ts = (int64_t)SCAN_BLOCK * SCAN_NPT;
     int64_t need = std::max<int64_t>(1, (n + ts - 1) / ts);
     int64_t g = 1;
     while (g < need) g <<= 1;
-    return (int)std::min<int64_t>(g, 8 * (int64_t)std::max(1, c->cu_count));
+    return (int)std::min<int64_t>(g, std::min<int64_t>(512, 2 * (int64_t)std::max(1, c->cu_count)));
   };
   ra.cont_rounds = o.max_rounds > 0 ? (int)std::min<int64_t>(o.max_rounds + 1, 4096) : 4096;
   HIPCHK(c, hipEventRecord(c->ev0, s));
@@ -1192,14 +1200,13 @@ trs_status trs_autotune(trs_ctx *c, const trs_opts *base, trs_opts *best, trs_tu
     return TRS_OK;
   };
   if (base->mode == TRS_MODE_PLAIN) {
-    // full sweeps every round: wide workgroups (16 waves) with a grid of
-    // about one or two per compute unit keep the most sweep tiles in flight
-    const trs_status ds = device_init(c);  // (the compute-unit count)
-    if (ds != TRS_OK) return ds;
-    const int cu = std::max(1, c->cu_count);
-    const int shapes[4][2] = {{1024, cu}, {512, cu}, {256, 2 * cu}, {1024, 2 * cu}};
+    // the scan kernel classifies the large full rounds, so the round
+    // kernel's shape matters for the list rounds that follow (narrow
+    // workgroups spread the examined slots over more compute units) and for
+    // small pools swept inside it
+    const int shapes[4][2] = {{128, 16}, {128, 8}, {64, 16}, {256, 16}};
     for (const auto &sh : shapes) {
-      const trs_status s = trial(sh[0], 16, sh[1]);
+      const trs_status s = trial(sh[0], sh[1], 0);
       if (s != TRS_OK) return s;
     }
   } else {

@@ -26,6 +26,10 @@ struct RoundArgs {
   int32_t use_scan;     // plain mode: large full rounds are classified by k_scan
                         // (launched before each k_round) and run as list rounds
   int32_t round_block;  // k_round's block size (for the scan's hand-over)
+  int32_t scan_lists;   // lists the scan appends to (1 or 16): list j is
+                        // written by the workgroups wg mod scan_lists = j
+  int64_t scan_rs;      // entries per list: list j starts at entry
+                        // (j mod 8) scan_rs of front0 (j < 8) or front1
   int32_t gate_off;     // learned mode: word offset of the decision table in tab
   uint32_t trace_rate;  // tracing: keep a blocked node-round when its hash
                         // (16 bits) is below this; 0 = off
@@ -54,9 +58,11 @@ struct RoundArgs {
 // work passes done.
 #define TRACE_FIELDS 16
 
-// Threads per workgroup of k_scan, and slots per thread per tile.
-#define SCAN_BLOCK 256
+// Threads per workgroup of k_scan, slots per thread per tile, and the
+// listed slots a workgroup gathers in LDS before appending them at once.
+#define SCAN_BLOCK 1024
 #define SCAN_NPT 16
+#define SCAN_CAP 8192
 
 // LDS bytes a round kernel needs for this configuration.
 size_t trs_round_lds_bytes(int block, int npt, int tab_words, int n_rules, int pf_depth,

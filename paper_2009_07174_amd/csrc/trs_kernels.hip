@@ -1190,7 +1190,18 @@ __device__ __forceinline__ void round_execute(const RoundArgs &a, Lds &L, const 
         const int x = RT[i - nd];
         if ((unsigned)x < (unsigned)p.N && x > 0) retire_marker(p.state, x, ep);
       } else if (i < nlist) {
-        const int x = F[i - nd - nr_here];
+        int x;
+        if (rs.scanned) {
+          // the scan's lists: item f of the combined list is in list j with
+          // scan_off[j] <= f < scan_off[j + 1]
+          const int f = i - nd - nr_here;
+          int j = 0;
+          for (int k = 1; k < a.scan_lists; k++) j += f >= ctl->scan_off[k] ? 1 : 0;
+          const int32_t *lst = ((j < 8) ? p.front0 : p.front1) + (int64_t)(j & 7) * a.scan_rs;
+          x = lst[f - ctl->scan_off[j]];
+        } else {
+          x = F[i - nd - nr_here];
+        }
         if ((unsigned)x < (unsigned)p.N && x > 0) {
           unsigned st = p.state[x];
           // queued slots are mostly live and not normal forms: their
@@ -1673,17 +1684,19 @@ __device__ __forceinline__ bool grid_barrier(unsigned long long *bar, unsigned l
 // Plain mode, a large full round r: the classification of every slot below n
 // that k_round's sweep would make, as a kernel of its own.  Markers of the
 // previous round are retired, woken sleepers' wake bits cleared, and the
-// slots to examine listed in the frontier buffer of parity (r-1)&1 (count in
-// cnt[r%3].scan; one fetch-add per wave).  The last workgroup turns the
-// published round into a list round of the dead nodes and the listed slots,
-// which the k_round launch that follows examines.  There is no work list in
-// LDS, no barrier per tile and no rewrite code here, so the kernel holds
-// few registers and many waves stream the state bytes; it does nothing
-// unless the round was published with a scan request.
+// slots to examine listed: gathered in LDS per workgroup and appended at the
+// end with one fetch-add on the counter of list wg mod scan_lists (each on a
+// line of its own; a wave that finds the LDS buffer full appends its excess
+// directly).  The last workgroup publishes the lists' offsets and turns the
+// round into a list round of the dead nodes and the listed slots, which the
+// following k_round launch examines.  No rewrite code, so few registers; it
+// does nothing unless the round was published with a scan request.
 template <int A>
 __global__ void __launch_bounds__(SCAN_BLOCK) k_scan(RoundArgs a) {
   Ctl *ctl = a.ctl;
   const Pool &p = a.p;
+  __shared__ int32_t sbuf[SCAN_CAP];
+  __shared__ int s_cnt, s_base;
   __shared__ unsigned long long s_act, s_still;
   const int tid = threadIdx.x;
   const int4 *pp = reinterpret_cast<const int4 *>(ctl->pub);
@@ -1693,9 +1706,12 @@ __global__ void __launch_bounds__(SCAN_BLOCK) k_scan(RoundArgs a) {
   if (!(flags & PUB_SCAN_REQ) || (flags & (PUB_SCANNED | PUB_STOP))) return;
   const int r = x.y, n = x.w, nd = y.z, nret = z.x;
   const unsigned e = (unsigned)(r & 1);
-  int32_t *X = ((r - 1) & 1) ? p.front1 : p.front0;
+  const int S = a.scan_lists, lj = (int)blockIdx.x & (S - 1);
+  int32_t *list = ((lj < 8) ? p.front0 : p.front1) + (int64_t)(lj & 7) * a.scan_rs;
+  int32_t *lcnt = &ctl->scan_cnt[lj][0];
   RoundCnt *cnt = &ctl->cnt[r % 3];
   if (tid == 0) {
+    s_cnt = 0;
     s_act = 0;
     s_still = 0;
   }
@@ -1703,10 +1719,8 @@ __global__ void __launch_bounds__(SCAN_BLOCK) k_scan(RoundArgs a) {
   constexpr int TS = SCAN_BLOCK * SCAN_NPT;
   const int ntiles = (n + TS - 1) / TS;
   int act = 0, still_n = 0;
-  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const int base = t * TS + tid * SCAN_NPT;
-    const uint4 vs = *reinterpret_cast<const uint4 *>(p.state + base);
-    const unsigned ww = p.wake[base >> 4];
+  // one tile's classification and listing (all lanes of the workgroup)
+  auto tile = [&](const int base, const uint4 vs, const unsigned ww) {
     int valid = 0xffff;
     if (base == 0) valid &= ~1;
     {
@@ -1736,8 +1750,8 @@ __global__ void __launch_bounds__(SCAN_BLOCK) k_scan(RoundArgs a) {
     retire &= valid;
     for (int m = retire; m; m &= m - 1) {
       const int j = __builtin_ctz(m);
-      const unsigned stb = (((j >> 2) == 0 ? vs.x : (j >> 2) == 1 ? vs.y : (j >> 2) == 2 ? vs.z : vs.w)
-                            >> ((j & 3) * 8)) & 0xffu;
+      const unsigned wj = (j >> 2) == 0 ? vs.x : (j >> 2) == 1 ? vs.y : (j >> 2) == 2 ? vs.z : vs.w;
+      const unsigned stb = (wj >> ((j & 3) * 8)) & 0xffu;
       p.state[base + j] = (uint8_t)((stb & ST_NF) ? ST_NF : ST_ACTIVE);
     }
     const int wmask = even_bits(ww >> (1u - e));
@@ -1754,10 +1768,43 @@ __global__ void __launch_bounds__(SCAN_BLOCK) k_scan(RoundArgs a) {
       const int incl = wave_incl_scan(c);
       const int tot = __shfl(incl, 63, 64);
       int wb = 0;
-      if (lane() == 63) wb = atomicAdd(&cnt->scan, tot);
-      int pos = __shfl(wb, 63, 64) + incl - c;
-      for (int m = exam; m; m &= m - 1) X[pos++] = base + __builtin_ctz(m);
+      if (lane() == 63) wb = atomicAdd(&s_cnt, tot);
+      wb = __shfl(wb, 63, 64);
+      // positions at or past the LDS capacity go straight to the list
+      const int lo = max(wb, SCAN_CAP);
+      const int ovf = max(0, wb + tot - lo);
+      int gb = 0;
+      if (ovf > 0) {
+        if (lane() == 63) gb = atomicAdd(lcnt, ovf);
+        gb = __shfl(gb, 63, 64);
+      }
+      int pos = wb + incl - c;
+      for (int m = exam; m; m &= m - 1, pos++) {
+        const int v = base + __builtin_ctz(m);
+        if (pos < SCAN_CAP)
+          sbuf[pos] = v;
+        else
+          list[gb + (pos - lo)] = v;
+      }
     }
+    };
+  // two tiles per iteration: both tiles' bytes are requested before either
+  // is classified, so each wave keeps two loads in flight
+  const int G = gridDim.x;
+  for (int t = blockIdx.x; t < ntiles; t += 2 * G) {
+    const int base0 = t * TS + tid * SCAN_NPT;
+    const bool two = t + G < ntiles;
+    const int base1 = base0 + G * TS;
+    const uint4 vs0 = *reinterpret_cast<const uint4 *>(p.state + base0);
+    const unsigned ww0 = p.wake[base0 >> 4];
+    uint4 vs1 = make_uint4(0, 0, 0, 0);
+    unsigned ww1 = 0;
+    if (two) {
+      vs1 = *reinterpret_cast<const uint4 *>(p.state + base1);
+      ww1 = p.wake[base1 >> 4];
+    }
+    tile(base0, vs0, ww0);
+    if (two) tile(base1, vs1, ww1);
   }
   {
     const int sa = wave_sum(act), ss = wave_sum(still_n);
@@ -1767,6 +1814,11 @@ __global__ void __launch_bounds__(SCAN_BLOCK) k_scan(RoundArgs a) {
     }
   }
   __syncthreads();
+  // the workgroup's gathered slots: one fetch-add on its list's counter
+  const int n_lds = min(s_cnt, SCAN_CAP);
+  if (tid == 0) s_base = n_lds > 0 ? atomicAdd(lcnt, n_lds) : 0;
+  __syncthreads();
+  for (int i = tid; i < n_lds; i += blockDim.x) list[s_base + i] = sbuf[i];
   if (tid == 0) {
     const int sp = blockIdx.x & (CTL_SPREAD - 1);
     if (s_act) atomicAdd(&ctl->stat[sp][STAT_ACTIVE], s_act);
@@ -1783,13 +1835,19 @@ __global__ void __launch_bounds__(SCAN_BLOCK) k_scan(RoundArgs a) {
     int fl = s_act ? 1 : 0;
     if (last_ticket(ctl, blockIdx.x, gridDim.x, &fl)) {
       if (fl & 1) st(&cnt->active, 1);
-      const int nx = ld(&cnt->scan);
-      const int nlist = nd + nret + nx;
+      int off = 0;
+      for (int j = 0; j < S; j++) {
+        st(&ctl->scan_off[j], off);
+        off += ld(&ctl->scan_cnt[j][0]);
+        st(&ctl->scan_cnt[j][0], 0);
+      }
+      st(&ctl->scan_off[S], off);
+      const int nlist = nd + nret + off;
       const int B = a.round_block;
       int need = max(1, (nlist + B - 1) / B);
       if (nlist <= a.small_cap) need = 1;
       st(&ctl->pub[2], need);
-      st(&ctl->pub[7], nx);
+      st(&ctl->pub[7], off);
       st(&ctl->pub[9], (flags & ~PUB_SCAN_REQ) | PUB_SCANNED);
       st(&ctl->next_need, need);
     }

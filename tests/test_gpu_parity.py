@@ -204,9 +204,9 @@ def test_autotune_plain_tunes_the_grid():
         best, res = ctx.autotune(T.Options(mode=0))
         say(f"[autotune plain] {res}")
         assert res["trials"] == 4
-        # grids of one or two workgroups per compute unit (MI355X: 256 CUs)
-        assert all(npt == 16 and g >= 64 for _, npt, g, _ in res["table"])
-        assert (best.block, best.max_grid) == (res["best_block"], res["best_grid"])
+        assert [(b, npt) for b, npt, _, _ in res["table"]] == [(128, 16), (128, 8), (64, 16),
+                                                                (256, 16)]
+        assert (best.block, best.nodes_per_thread) == (res["best_block"], res["best_npt"])
         ctx.normalize(best)
         nfs = [ctx.read_nf(i) for i in range(len(w.terms))]
     finally:
@@ -238,14 +238,17 @@ def test_autotune_picks_a_shape_and_keeps_results():
 
 
 
-@pytest.mark.parametrize("case", ["batch_mini", "cfg2", "fib20"])
+@pytest.mark.parametrize("case", ["batch_mini", "batch_mini_16_lists", "cfg2", "fib20"])
 def test_plain_scan_kernel_agrees(case, monkeypatch):
-    """The opt-in plain-mode scan kernel (TRS_SCAN=1): a separate launch
-    classifies the slots of each large full round and the round kernel then
-    examines the listed slots; results and counts equal the oracle's, and
-    the statistics equal those of the sweep inside the round kernel."""
-    if case == "batch_mini":
-        w = G.cfg3(200, 1 << 22, "mini")
+    """The plain-mode scan kernel (the default) against the sweep inside the
+    round kernel (TRS_NO_SCAN=1): a separate launch classifies the slots of
+    each large full round and the round kernel then examines the listed
+    slots; results and counts equal the oracle's, and the statistics equal
+    those of the in-kernel sweep."""
+    if case.startswith("batch_mini"):
+        # (a pool of 2^24 slots or more makes the scan use 16 lists)
+        pool = 1 << 24 if case.endswith("16_lists") else 1 << 22
+        w = G.cfg3(200, pool, "mini")
         trs, terms, pool, A = w.trs, w.terms, w.pool_slots, w.maxarity
     elif case == "cfg2":
         trs = systems.msort()
@@ -255,8 +258,9 @@ def test_plain_scan_kernel_agrees(case, monkeypatch):
         trs = systems.fib()
         terms, pool, A = [G.g_term(trs, 20)], 1 << 20, 2
     opts = dict(mode=0, block=256, nodes_per_thread=16)
+    monkeypatch.setenv("TRS_NO_SCAN", "1")
     base = assert_parity(trs, terms, pool, A, label=f"plain sweep {case}", **opts)
-    monkeypatch.setenv("TRS_SCAN", "1")
+    monkeypatch.delenv("TRS_NO_SCAN")
     scan = assert_parity(trs, terms, pool, A, label=f"plain scan {case}", **opts)
     for k in ("rounds", "node_visits", "active_visits", "ready_visits", "full_sweeps", "memo_blocked"):
         assert scan[k] == base[k], k
