@@ -78,8 +78,11 @@ __device__ __forceinline__ void st(int32_t *p, int v) {
 // workgroup set each.  The caller has waited for its own memory operations
 // first.
 __device__ __forceinline__ bool last_ticket(Ctl *ctl, int wg, int gt, int *flags) {
+  // up to 32 workgroups: one level (a second fetch-add would cost a
+  // dependent round trip, more than 32 same-address ones)
   int ng = 1;
-  while (ng * ng < gt && ng < TICKET_GROUPS) ng <<= 1;
+  if (gt > 32)
+    while (ng * ng < gt && ng < TICKET_GROUPS) ng <<= 1;
   const int g = wg & (ng - 1);
   const int gsize = (gt - g + ng - 1) / ng;  // workgroups w < gt with w mod ng = g
   auto enc = [](int f) {
@@ -93,6 +96,10 @@ __device__ __forceinline__ bool last_ticket(Ctl *ctl, int wg, int gt, int *flags
   const unsigned long long v1 = atomicAdd(c1, a1) + a1;
   if ((int)(v1 & 0xffffffffu) != gsize) return false;
   __hip_atomic_store(c1, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (ng == 1) {
+    *flags = dec(v1);
+    return true;
+  }
   unsigned long long *c2 = &ctl->tickets[TICKET_GROUPS][0];
   const unsigned long long a2 = enc(dec(v1));
   const unsigned long long v2 = atomicAdd(c2, a2) + a2;
@@ -635,6 +642,11 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
       nfset = true;
     } else {
       const int32_t *rtab = tab + TAB_SYM + a.n_sym + first;
+      // the last node below the arguments read during matching: its slot,
+      // symbol and entries, read together (the rules of a symbol often test
+      // the same node, and its entries bind the variables below it)
+      int cc = 0, chh = -1;
+      VecA<A> cargs = (VecA<A>)(0);
       for (int i = 0; i < nr && prog < 0; i++) {
         const int pg = rtab[i];
         const int npat = tab[pg] & 15;
@@ -651,13 +663,23 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
             if (A <= 4) d1 |= (unsigned)(pos + 1) << (3 * k);  // (gc is kept for A <= 4)
           } else {
             const int jp = (int)((d1 >> (3 * par)) & 7);
-            c = jp ? gc[(jp - 1) * A + pos] : p.args[(int64_t)pslot(par) * A + pos];
+            const int sp = pslot(par);
+            c = jp ? gc[(jp - 1) * A + pos]
+                   : (sp == cc ? cargs[pos] : p.args[(int64_t)sp * A + pos]);
             if ((unsigned)c >= (unsigned)N || c == 0) {  // broken invariant: stop safely
               st(&cnt->err, -9);
-              c = pslot(par);
+              c = sp;
               ok = false;
             }
-            if (!isvar && ok) h = p.hss[c];
+            if (!isvar && ok) {
+              if (c != cc) {
+                cc = c;
+                chh = p.hss[c];
+#pragma unroll
+                for (int q = 0; q < A; q++) cargs[q] = p.args[(int64_t)c * A + q];
+              }
+              h = chh;
+            }
           }
           ps[k - 1] = c;
           if (!isvar && h != (pe >> 16)) ok = false;
