@@ -206,6 +206,9 @@ struct Lds {
   // phase timestamps of this workgroup's current round (per-workgroup phase
   // trace only), written to the trace buffer when the round ends
   unsigned long long *tstamp;
+  // a scanned round: start offsets of the scan's lists in the round's list
+  // (entry scan_lists: their total)
+  int32_t *soff;
   Queue qd, qf, qr;  // dead, frontier, retire
 };
 
@@ -1042,11 +1045,19 @@ __device__ __forceinline__ RoundState round_prepare(const RoundArgs &a, const Ld
   // the published line and (load_tab) the tables are read together: one
   // dependent read at the start of a launch instead of two
   int4 x, y, z;
+  int2 sc[16];  // the scan's list counts and flags (plain mode), read with the line
   if (from_pub && threadIdx.x == 0) {
     const int4 *pp = reinterpret_cast<const int4 *>(a.ctl->pub);
     x = pp[0];
     y = pp[1];
     z = pp[2];
+    // (plain loads: written by the launch before, as the published line)
+    if (a.use_scan) {
+#pragma unroll
+      for (int j = 0; j < 16; j++)
+        sc[j] = j < a.scan_lists ? *reinterpret_cast<const int2 *>(&a.ctl->scan_cnt[j][0])
+                                 : make_int2(0, 0);
+    }
   }
   if (load_tab)
     for (int i = threadIdx.x; i < a.tab_words; i += blockDim.x) L.tab[i] = a.tab[i];
@@ -1063,6 +1074,23 @@ __device__ __forceinline__ RoundState round_prepare(const RoundArgs &a, const Ld
       bc[8] = z.x;
       bc[9] = z.y;
       L.misc[29] = z.z;  // the run's stamp base, kept for the whole launch
+      if ((z.y & PUB_SCAN_REQ) && !(z.y & PUB_STOP)) {
+        // the scan launched just before classified this round: its lists'
+        // counts give the list offsets and the number of listed slots
+        int off = 0, act = 0;
+#pragma unroll
+        for (int j = 0; j < 16; j++) {
+          if (j < a.scan_lists) {
+            L.soff[j] = off;
+            off += sc[j].x;
+            act |= sc[j].y;
+          }
+        }
+        L.soff[a.scan_lists] = off;
+        bc[7] = off;
+        bc[9] = (z.y & ~PUB_SCAN_REQ) | PUB_SCANNED;
+        L.misc[28] = act;  // a live non-normal-form slot was met
+      }
     } else {
       const RoundState t = round_state(a, r);
       bc[0] = 0;
@@ -1159,6 +1187,7 @@ __device__ __forceinline__ void round_execute(const RoundArgs &a, Lds &L, const 
       st(w, 0);
     // (a scanned round examined every slot; the scan counted its visits)
     st(&ctl->cnt[r3].full, (full || quiescent || rs.scanned) ? 1 : 0);
+    if (rs.scanned && L.misc[28]) st(&ctl->cnt[r3].active, 1);
     if ((unsigned long long)n > L.lstat[LSTAT_PEAK]) L.lstat[LSTAT_PEAK] = n;
     if (nd > 0) L.lstat[LSTAT_GC]++;
     if (full) L.lstat[LSTAT_FULL]++;
@@ -1218,9 +1247,9 @@ __device__ __forceinline__ void round_execute(const RoundArgs &a, Lds &L, const 
           // scan_off[j] <= f < scan_off[j + 1]
           const int f = i - nd - nr_here;
           int j = 0;
-          for (int k = 1; k < a.scan_lists; k++) j += f >= ctl->scan_off[k] ? 1 : 0;
+          for (int k = 1; k < a.scan_lists; k++) j += f >= L.soff[k] ? 1 : 0;
           const int32_t *lst = ((j < 8) ? p.front0 : p.front1) + (int64_t)(j & 7) * a.scan_rs;
-          x = lst[f - ctl->scan_off[j]];
+          x = lst[f - L.soff[j]];
         } else {
           x = F[i - nd - nr_here];
         }
@@ -1566,10 +1595,11 @@ __device__ __forceinline__ Lds setup_lds(const RoundArgs &a, int32_t *smem, bool
   L.misc = q + 3 * qc + 5 * B * a.pf_depth;
   L.lstat = reinterpret_cast<unsigned long long *>(L.misc + 64);
   L.tstamp = reinterpret_cast<unsigned long long *>(L.misc + 64 + 2 * 16);
-  L.rcnt = L.misc + 64 + 2 * 16 + 2 * TRACE_FIELDS;
+  L.soff = L.misc + 64 + 2 * 16 + 2 * TRACE_FIELDS;
+  L.rcnt = L.soff + 32;
   if (load_tab)
     for (int i = threadIdx.x; i < a.tab_words; i += B) L.tab[i] = a.tab[i];
-  for (int i = threadIdx.x; i < 64 + 2 * 16 + 2 * TRACE_FIELDS; i += B) L.misc[i] = 0;
+  for (int i = threadIdx.x; i < 64 + 2 * 16 + 2 * TRACE_FIELDS + 32; i += B) L.misc[i] = 0;
   for (int i = threadIdx.x; i < a.n_rules; i += B) L.rcnt[i] = 0;
   lds_sync();
   return L;
@@ -1603,6 +1633,7 @@ __global__ void __launch_bounds__(1024) k_round(RoundArgs a) {
   // workgroups at work, however large its grid.
   RoundState rs = round_prepare(a, L, 0, true, true);
   const int r0 = rs.r;  // the launch's first round
+  const bool scanned0 = rs.scanned;
   int r_exec = rs.r;    // the last round this workgroup executed (phase trace)
   if (rs.done) return;
   const int need0 = rs.need;
@@ -1653,6 +1684,14 @@ __global__ void __launch_bounds__(1024) k_round(RoundArgs a) {
         RoundCnt *c0 = &ctl->cnt[r0 % 3];
         if (flags & 1) st(&c0->active, 1);
         if (flags & 2) st(&c0->prog, 1);
+      }
+      if (scanned0) {
+        // every workgroup read the scan's counts at launch start: clear them
+        // for the next scan
+        for (int j = 0; j < a.scan_lists; j++) {
+          st(&ctl->scan_cnt[j][0], 0);
+          st(&ctl->scan_cnt[j][1], 0);
+        }
       }
       // last working workgroup of the launch: every round it covered is
       // complete.  It reads only counters kept with agent-scope atomics, so
@@ -1722,16 +1761,15 @@ __global__ void __launch_bounds__(SCAN_BLOCK) k_scan(RoundArgs a) {
   __shared__ unsigned long long s_act, s_still;
   const int tid = threadIdx.x;
   const int4 *pp = reinterpret_cast<const int4 *>(ctl->pub);
-  const int4 x = pp[0], y = pp[1], z = pp[2];  // done r need n | fs0 fs1 nd nfront | nret flags
+  const int4 x = pp[0], z = pp[2];  // done r need n | (pp[1]) | nret flags
   if (x.x != 0) return;
   const int flags = z.y;
   if (!(flags & PUB_SCAN_REQ) || (flags & (PUB_SCANNED | PUB_STOP))) return;
-  const int r = x.y, n = x.w, nd = y.z, nret = z.x;
+  const int r = x.y, n = x.w;
   const unsigned e = (unsigned)(r & 1);
   const int S = a.scan_lists, lj = (int)blockIdx.x & (S - 1);
   int32_t *list = ((lj < 8) ? p.front0 : p.front1) + (int64_t)(lj & 7) * a.scan_rs;
   int32_t *lcnt = &ctl->scan_cnt[lj][0];
-  RoundCnt *cnt = &ctl->cnt[r % 3];
   if (tid == 0) {
     s_cnt = 0;
     s_act = 0;
@@ -1810,23 +1848,26 @@ __global__ void __launch_bounds__(SCAN_BLOCK) k_scan(RoundArgs a) {
       }
     }
     };
-  // two tiles per iteration: both tiles' bytes are requested before either
-  // is classified, so each wave keeps two loads in flight
+  // four tiles per iteration: their bytes are requested before any is
+  // classified, so each wave keeps four loads in flight
+  constexpr int U = 4;
   const int G = gridDim.x;
-  for (int t = blockIdx.x; t < ntiles; t += 2 * G) {
-    const int base0 = t * TS + tid * SCAN_NPT;
-    const bool two = t + G < ntiles;
-    const int base1 = base0 + G * TS;
-    const uint4 vs0 = *reinterpret_cast<const uint4 *>(p.state + base0);
-    const unsigned ww0 = p.wake[base0 >> 4];
-    uint4 vs1 = make_uint4(0, 0, 0, 0);
-    unsigned ww1 = 0;
-    if (two) {
-      vs1 = *reinterpret_cast<const uint4 *>(p.state + base1);
-      ww1 = p.wake[base1 >> 4];
+  for (int t = blockIdx.x; t < ntiles; t += U * G) {
+    uint4 vs[U];
+    unsigned ww[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      vs[u] = make_uint4(0, 0, 0, 0);
+      ww[u] = 0;
+      if (t + u * G < ntiles) {
+        const int b = (t + u * G) * TS + tid * SCAN_NPT;
+        vs[u] = *reinterpret_cast<const uint4 *>(p.state + b);
+        ww[u] = p.wake[b >> 4];
+      }
     }
-    tile(base0, vs0, ww0);
-    if (two) tile(base1, vs1, ww1);
+#pragma unroll
+    for (int u = 0; u < U; u++)
+      if (t + u * G < ntiles) tile((t + u * G) * TS + tid * SCAN_NPT, vs[u], ww[u]);
   }
   {
     const int sa = wave_sum(act), ss = wave_sum(still_n);
@@ -1850,30 +1891,10 @@ __global__ void __launch_bounds__(SCAN_BLOCK) k_scan(RoundArgs a) {
       atomicAdd((unsigned *)&ctl->full_sweeps, 1u);
     }
   }
-  // as in k_round: each wave's fetch-adds complete before the ticket
-  __builtin_amdgcn_s_waitcnt(0);
-  __syncthreads();
-  if (tid == 0) {
-    int fl = s_act ? 1 : 0;
-    if (last_ticket(ctl, blockIdx.x, gridDim.x, &fl)) {
-      if (fl & 1) st(&cnt->active, 1);
-      int off = 0;
-      for (int j = 0; j < S; j++) {
-        st(&ctl->scan_off[j], off);
-        off += ld(&ctl->scan_cnt[j][0]);
-        st(&ctl->scan_cnt[j][0], 0);
-      }
-      st(&ctl->scan_off[S], off);
-      const int nlist = nd + nret + off;
-      const int B = a.round_block;
-      int need = max(1, (nlist + B - 1) / B);
-      if (nlist <= a.small_cap) need = 1;
-      st(&ctl->pub[2], need);
-      st(&ctl->pub[7], off);
-      st(&ctl->pub[9], (flags & ~PUB_SCAN_REQ) | PUB_SCANNED);
-      st(&ctl->next_need, need);
-    }
-  }
+  // the flag that a live non-normal-form slot was met, on the line of the
+  // workgroup's list (the round kernel that follows reads the counts and
+  // flags at launch start; the kernel boundary orders them)
+  if (tid == 0 && s_act) st(&ctl->scan_cnt[lj][1], 1);
 }
 
 template <int A>
@@ -1915,7 +1936,7 @@ size_t trs_round_lds_bytes(int block, int npt, int tab_words, int n_rules, int p
                            int qbuf) {
   size_t words = (size_t)((tab_words + 3) & ~3) + (size_t)block * npt + block +
                  (size_t)3 * qbuf * block + (size_t)5 * block * pf_depth + 64 + 2 * 16 +
-                 2 * TRACE_FIELDS + (size_t)n_rules;
+                 2 * TRACE_FIELDS + 32 + (size_t)n_rules;
   return words * sizeof(int32_t);
 }
 

@@ -161,11 +161,10 @@ struct Ctl {
   // live non-normal-form slot (bits 32-47) and made progress (48-63), so
   // the last one knows the round's two flags without a store per workgroup)
   unsigned long long tickets[TICKET_GROUPS + 1][16];
-  // plain-mode scan: slots listed in each of up to 16 lists (a counter per
-  // 128-byte line), and the lists' start offsets in the round's combined
-  // list (published by the scan's last workgroup)
+  // plain-mode scan: per list (up to 16, each on a 128-byte line of its
+  // own) the slots listed and whether a live non-normal-form slot was met;
+  // read by the round kernel that follows, cleared by its last workgroup
   int32_t scan_cnt[16][32];
-  int32_t scan_off[32];
 };
 
 struct Pool {
