@@ -1634,6 +1634,7 @@ __global__ void __launch_bounds__(1024) k_round(RoundArgs a) {
   RoundState rs = round_prepare(a, L, 0, true, true);
   const int r0 = rs.r;  // the launch's first round
   const bool scanned0 = rs.scanned;
+  int rr_local = r0 + 1;  // the round the next launch starts with
   int r_exec = rs.r;    // the last round this workgroup executed (phase trace)
   if (rs.done) return;
   const int need0 = rs.need;
@@ -1662,10 +1663,8 @@ __global__ void __launch_bounds__(1024) k_round(RoundArgs a) {
         break;
       }
     }
-    flush_stats(a, L);
-    if (alone && tid == 0)
-      __hip_atomic_store(&ctl->r_reached, rs.stop || rs.need == 1 ? rs.r + 1 : rs.r,
-                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // (workgroup 0 alone: the round after the last one it ran)
+    if (alone) rr_local = max(r0 + 1, rs.stop || rs.need == 1 ? rs.r + 1 : rs.r);
   }
   // Every wave waits for its own memory operations of the launch (the round
   // counters' fetch-adds among them) to complete before the workgroup takes
@@ -1695,8 +1694,9 @@ __global__ void __launch_bounds__(1024) k_round(RoundArgs a) {
       }
       // last working workgroup of the launch: every round it covered is
       // complete.  It reads only counters kept with agent-scope atomics, so
-      // it needs no fence either.
-      const int rr = max(ld(&ctl->r_cur) + 1, ld(&ctl->r_reached));
+      // it needs no fence either.  (With more than one workgroup the launch
+      // ran round r0 alone; with one, that workgroup is this one.)
+      const int rr = rr_local;
       const RoundState nx = round_state(a, rr);
       publish(ctl, nx);
       if (a.trace_max)
@@ -1708,6 +1708,9 @@ __global__ void __launch_bounds__(1024) k_round(RoundArgs a) {
     }
     tflush(a, L, r_exec);
   }
+  // the launch's statistics, after the ticket: only the host reads them,
+  // after the run, so they stay off the launch's critical path
+  flush_stats(a, L);
 }
 
 // Device-wide barrier for the persistent kernel.  The host zeroes *bar
