@@ -920,9 +920,10 @@ trs_status trs_normalize(trs_ctx *c, const trs_opts *opts_in, trs_stats *stats) 
   int P = 1;               // chunks (or persistent launches) per poll
   const int KP = o.rounds_per_poll ? o.rounds_per_poll : 64;  // persistent rounds per launch
   // one workgroup runs rounds alone while their lists hold at most this
-  // many items (a few passes of the workgroup), continuing for up to
-  // cont_rounds rounds inside one launch
-  ra.small_cap = 4 * B;
+  // many items (one pass of the workgroup: on the 4096-term batch a launch
+  // beats two or more passes of one workgroup, 2.62 s against 2.75 s at
+  // four), continuing for up to cont_rounds rounds inside one launch
+  ra.small_cap = B;
   // plain mode: large full rounds are classified by k_scan, launched before
   // each round launch, and run as list rounds (not in the persistent form,
   // nor when tracing; TRS_NO_SCAN=1 keeps the sweep inside k_round).  On the
