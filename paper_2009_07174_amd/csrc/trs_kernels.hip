@@ -1557,11 +1557,13 @@ __device__ __forceinline__ void round_execute(const RoundArgs &a, Lds &L, const 
 
 // Add this workgroup's statistics of the launch to the control block (once,
 // at the end of the launch).
-__device__ __forceinline__ void flush_stats(const RoundArgs &a, const Lds &L) {
+// Threads t0, t0 + 1, ... add the statistics to the control block (no
+// barrier: the caller has synchronised the workgroup).
+__device__ __forceinline__ void stats_out(const RoundArgs &a, const Lds &L, int t0) {
   Ctl *ctl = a.ctl;
   const int wg = blockIdx.x, tid = threadIdx.x;
-  lds_sync();
-  if (tid == 0) {
+  if (tid < t0) return;
+  if (tid == t0) {
     const int sp = wg & (CTL_SPREAD - 1);
     for (int k = 0; k < CTL_NSTAT; k++)
       if (L.lstat[k]) atomicAdd(&ctl->stat[sp][k], L.lstat[k]);
@@ -1570,10 +1572,15 @@ __device__ __forceinline__ void flush_stats(const RoundArgs &a, const Lds &L) {
       atomicAdd((unsigned *)&ctl->full_sweeps, (unsigned)L.lstat[LSTAT_FULL]);
     if (L.lstat[LSTAT_PEAK]) atomicMax(&ctl->peak_n, (int)L.lstat[LSTAT_PEAK]);
   }
-  for (int i = tid; i < a.n_rules; i += blockDim.x) {
+  for (int i = tid - t0; i < a.n_rules; i += blockDim.x - t0) {
     const int c = L.rcnt[i];
     if (c) atomicAdd(&ctl->rule_apps[wg & (RULE_SPREAD - 1)][i], (unsigned long long)c);
   }
+}
+
+__device__ __forceinline__ void flush_stats(const RoundArgs &a, const Lds &L) {
+  lds_sync();
+  stats_out(a, L, 0);
 }
 
 __device__ __forceinline__ Lds setup_lds(const RoundArgs &a, int32_t *smem, bool load_tab) {
@@ -1675,6 +1682,11 @@ __global__ void __launch_bounds__(1024) k_round(RoundArgs a) {
   // each of thousands of workgroups per round it cost more than the sweep.
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
+  // the launch's statistics: only the host reads them, after the run, so
+  // the waves after the first add them while the first takes the ticket
+  // (with one wave, after the ticket)
+  const int t_stats = blockDim.x > 64 ? 64 : 0;
+  if (t_stats) stats_out(a, L, t_stats);
   if (tid == 0) {
     int flags = (L.misc[32] ? 1 : 0) | (L.misc[33] ? 2 : 0);  // (set only by rounds run by more
                                                                // than one workgroup)
@@ -1708,9 +1720,7 @@ __global__ void __launch_bounds__(1024) k_round(RoundArgs a) {
     }
     tflush(a, L, r_exec);
   }
-  // the launch's statistics, after the ticket: only the host reads them,
-  // after the run, so they stay off the launch's critical path
-  flush_stats(a, L);
+  if (!t_stats) stats_out(a, L, 0);
 }
 
 // Device-wide barrier for the persistent kernel.  The host zeroes *bar
