@@ -956,19 +956,38 @@ trs_status trs_normalize(trs_ctx *c, const trs_opts *opts_in, trs_stats *stats) 
   const auto t_start = std::chrono::steady_clock::now();
   double last_report = 0.0;
   int64_t front_est = 0;
+  // the launches skip a round whose lists or sweep a grid four times larger
+  // would still take in four passes (k_round, k_scan: grid_too_small): the
+  // estimates above come from the last poll, and a term that grows fast
+  // (a tree that doubles every round) would otherwise run many rounds on a
+  // grid sized for its first.  An interval that made no progress raises the
+  // grid (at least doubling it, so the loop ends); one that did lowers that
+  // floor again.
+  int g_floor = 1;
+  int64_t r_polled = -1;
+  int g_prev = -1, sg_prev = -1;  // the previous interval's launch shape
   trs_status result = TRS_OK;
   for (;;) {
     int g = grid_for(n_est);
     if (o.mode == TRS_MODE_FRONTIER && front_est > 0) {
       // frontier rounds need only as many workgroups as queued items (twice
-      // the last observed count, as a power of two); the rare full sweeps
-      // stride over all tiles with the same grid.  A persistent grid also
-      // pays its device-wide barrier per workgroup.  (Learned mode keeps the
-      // full grid: its periodic sweeps are frequent.)
+      // the last observed count, as a power of two; a list takes a pass per
+      // B items, a sweep one per B * npt slots, so this may exceed the sweep's
+      // grid); the rare full sweeps stride over all tiles with the same grid.
+      // A persistent grid also pays its device-wide barrier per workgroup.
+      // (Learned mode keeps the full grid: its periodic sweeps are frequent.)
       int64_t need = std::max<int64_t>(8, (2 * front_est + B - 1) / B);
       int64_t gg = 1;
       while (gg < need) gg <<= 1;
-      g = (int)std::min<int64_t>(gg, g);
+      g = (int)std::min<int64_t>(gg, gmax);
+    }
+    g = std::min(gmax, std::max(g, g_floor));
+    if (o.persistent || g >= gmax) {
+      ra.grow_list = ra.grow_full = 0;
+    } else {
+      const int64_t gl = (int64_t)g * B * 4, gf = (int64_t)g * TILE * 4;
+      ra.grow_list = gl <= INT32_MAX ? (int)gl : 0;
+      ra.grow_full = gf <= INT32_MAX ? (int)gf : 0;
     }
     if (o.persistent) {
       for (int i = 0; i < P; i++) {
@@ -979,35 +998,50 @@ trs_status trs_normalize(trs_ctx *c, const trs_opts *opts_in, trs_stats *stats) 
       }
     } else {
       const int sg = ra.use_scan ? scan_grid_for(n_est) : 0;
-      if (!c->gexec || c->g_grid != g || c->g_sgrid != sg || c->g_block != B || c->g_k != K ||
-          c->g_lds != lds ||
-          std::memcmp(&c->g_args, &ra, sizeof(ra)) != 0) {
-        if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
-        if (c->graph) (void)hipGraphDestroy(c->graph);
-        c->gexec = nullptr;
-        c->graph = nullptr;
-        HIPCHK(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        for (int k = 0; k < K; k++) {
-          hipError_t e = ra.use_scan ? trs_launch_scan(A, ra, sg, s) : hipSuccess;
-          if (e == hipSuccess) e = trs_launch_round(A, ra, g, B, s);
-          if (e != hipSuccess) {
-            hipGraph_t junk;
-            (void)hipStreamEndCapture(s, &junk);
-            return c->fail(TRS_E_HIP, std::string("capture: ") + hipGetErrorString(e));
-          }
+      const bool cached = c->gexec && c->g_grid == g && c->g_sgrid == sg && c->g_block == B &&
+                          c->g_k == K && c->g_lds == lds &&
+                          std::memcmp(&c->g_args, &ra, sizeof(ra)) == 0;
+      // a launch shape is captured once the previous interval used it too:
+      // while the grid still changes from poll to poll (a term that grows
+      // fast) plain launches cost less than a capture per interval
+      const bool stable = g == g_prev && sg == sg_prev;
+      g_prev = g;
+      sg_prev = sg;
+      if (!cached && !stable) {
+        for (int i = 0; i < P * K; i++) {
+          if (ra.use_scan) HIPCHK(c, trs_launch_scan(A, ra, sg, s));
+          HIPCHK(c, trs_launch_round(A, ra, g, B, s));
         }
-        HIPCHK(c, hipStreamEndCapture(s, &c->graph));
-        HIPCHK(c, hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
-        c->g_grid = g;
-        c->g_sgrid = sg;
-        c->g_block = B;
-        c->g_k = K;
-        c->g_lds = lds;
-        std::memcpy(&c->g_args, &ra, sizeof(ra));
-      }
-      for (int i = 0; i < P; i++) {
-        HIPCHK(c, hipGraphLaunch(c->gexec, s));
-        launches += K;
+        launches += (int64_t)P * K;
+      } else {
+        if (!cached) {
+          if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+          if (c->graph) (void)hipGraphDestroy(c->graph);
+          c->gexec = nullptr;
+          c->graph = nullptr;
+          HIPCHK(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+          for (int k = 0; k < K; k++) {
+            hipError_t e = ra.use_scan ? trs_launch_scan(A, ra, sg, s) : hipSuccess;
+            if (e == hipSuccess) e = trs_launch_round(A, ra, g, B, s);
+            if (e != hipSuccess) {
+              hipGraph_t junk;
+              (void)hipStreamEndCapture(s, &junk);
+              return c->fail(TRS_E_HIP, std::string("capture: ") + hipGetErrorString(e));
+            }
+          }
+          HIPCHK(c, hipStreamEndCapture(s, &c->graph));
+          HIPCHK(c, hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
+          c->g_grid = g;
+          c->g_sgrid = sg;
+          c->g_block = B;
+          c->g_k = K;
+          c->g_lds = lds;
+          std::memcpy(&c->g_args, &ra, sizeof(ra));
+        }
+        for (int i = 0; i < P; i++) {
+          HIPCHK(c, hipGraphLaunch(c->gexec, s));
+          launches += K;
+        }
       }
     }
     HIPCHK(c, hipMemcpyAsync(c->h_ctl, c->d_ctl, small, hipMemcpyDeviceToHost, s));
@@ -1030,12 +1064,25 @@ trs_status trs_normalize(trs_ctx *c, const trs_opts *opts_in, trs_stats *stats) 
       result = c->fail(TRS_E_ROUNDS, "no normal form within max_rounds");
       break;
     }
-    // the extent at the start of the last issued round
-    n_est = std::max<int64_t>(n_est, c->h_ctl->peak_n);
+    // the extent at the start of the last issued round, and of the round
+    // published for the next launch
+    n_est = std::max<int64_t>(n_est, std::max(c->h_ctl->peak_n, c->h_ctl->pub[3]));
     front_est = 0;
     for (int k = 0; k < 3; k++)
       front_est = std::max<int64_t>(front_est, c->h_ctl->cnt[k].front + c->h_ctl->cnt[k].dead);
-    P = std::min(P * 2, o.rounds_per_poll ? 1 : 64);
+    if (r == r_polled) {
+      // no round ran: the grid was too small for the published round
+      int64_t want = 2 * (int64_t)g, need_pub = std::max(1, c->h_ctl->pub[2]), p2 = 1;
+      while (p2 < need_pub) p2 <<= 1;
+      g_floor = (int)std::min<int64_t>(gmax, std::max(want, p2));
+      P = 1;
+      if (progress) std::fprintf(stderr, "[trs] round %lld: grid %d -> at least %d\n",
+                                 (long long)r, g, g_floor);
+    } else {
+      g_floor = std::max(1, g_floor / 2);
+      P = std::min(P * 2, o.rounds_per_poll ? 1 : 64);
+    }
+    r_polled = r;
   }
   HIPCHK(c, hipEventRecord(c->ev1, s));
   HIPCHK(c, hipMemcpyAsync(c->h_ctl, c->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));

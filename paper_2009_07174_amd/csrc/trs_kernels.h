@@ -19,6 +19,13 @@ struct RoundArgs {
   int32_t nrounds;      // rounds a persistent launch may run
   int32_t cont_rounds;  // rounds workgroup 0 may continue alone in one launch
   int32_t small_cap;    // list items one workgroup takes on alone
+  // a larger grid exists (0: the launch's grid is the largest): a launch
+  // whose round lists more than grow_list items, or (plain and learned
+  // modes) sweeps more than grow_full slots, returns at once without
+  // executing it, so that the host sizes a larger grid from the published
+  // round
+  int32_t grow_list;
+  int32_t grow_full;
   int32_t mode;         // 0 full sweeps, 1 frontier by parent notification,
                         // 2 frontier chosen by the predictor (full sweep when
                         // the frontier is empty)

@@ -149,6 +149,23 @@ __device__ __forceinline__ int wave_reserve(bool pred, int32_t *ctr) {
   return pred ? base + __popcll(m & __lanemask_lt()) : -1;
 }
 
+// The lanes of the wave that execute this call (the active lanes) and add
+// the same delta d to the same count t are combined: the first of them gets
+// their number, the others 0; a lane that differs from the first gets 1.
+// The firings of one rule in a round on redexes that share a variable's
+// binding (a subterm shared by every node of a level, as in a tree that
+// doubles every round) all update one count, and same-address atomics
+// serialise at about 8 ns each: millions of them per round without this.
+__device__ __forceinline__ int wave_combine(int t, int d) {
+  const unsigned long long act = __ballot(1);
+  const int leader = __ffsll((long long)act) - 1;
+  const int tl = __shfl(t, leader, 64), dl = __shfl(d, leader, 64);
+  const bool m = t == tl && d == dl;
+  const unsigned long long same = __ballot(m);
+  if (!m) return 1;
+  return lane() == leader ? __popcll(same) : 0;
+}
+
 // inclusive prefix sum over the 64 lanes of a wave
 __device__ __forceinline__ int wave_incl_scan(int x) {
 #pragma unroll
@@ -849,17 +866,34 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
       }
     }
     // reference counts: increments first, then decrements (a decrement that
-    // reaches zero puts the node on the dead list)
-    for (int i = 0; i < npos; i++) {
+    // reaches zero puts the node on the dead list).  The first entry of each
+    // kind is combined over the wave's lanes that update the same count by
+    // the same amount (one atomic for all of them, issued by the first)
+    if (npos > 0) {
+      const int dw = tab[dl];
+      const int d = (int)(int8_t)((dw >> 8) & 0xff);
+      const int t = pslot(dw & 0xff);
+      const int c = wave_combine(t, d);
+      if (c) atomicAdd(&p.rc[t], c * d);
+    }
+    for (int i = 1; i < npos; i++) {
       const int dw = tab[dl + i];
       atomicAdd(&p.rc[pslot(dw & 0xff)], (int)(int8_t)((dw >> 8) & 0xff));
     }
     // decrements: the first NEG_BATCH are all issued before any result is
-    // examined, so their latencies (and the parent exchange's) overlap
+    // examined, so their latencies (and the parent exchange's) overlap; the
+    // combined one reaches zero only when the last reference goes
     constexpr int NEG_BATCH = 4;
     ivec4 dold, dslot;
+    if (nneg > 0) {
+      const int dw = tab[dl + npos];
+      const int d = (int)(int8_t)((dw >> 8) & 0xff);
+      dslot[0] = pslot(dw & 0xff);
+      const int c = wave_combine(dslot[0], d);
+      dold[0] = c ? atomicAdd(&p.rc[dslot[0]], c * d) + c * d : 1;
+    }
 #pragma unroll
-    for (int i = 0; i < NEG_BATCH; i++) {
+    for (int i = 1; i < NEG_BATCH; i++) {
       if (i < nneg) {
         const int dw = tab[dl + npos + i];
         const int d = (int)(int8_t)((dw >> 8) & 0xff);
@@ -1137,6 +1171,16 @@ __device__ __forceinline__ RoundState round_prepare(const RoundArgs &a, const Ld
   if (rs.ntiles <= 1 && rs.nlist <= a.small_cap) rs.need = 1;
   if (rs.stop) rs.need = 1;
   return rs;
+}
+
+// The round needs a larger grid than the launch's: more list items than
+// grow_list (not for a scanned round: its scan has run), or in plain and
+// learned modes a sweep (or a scan) of more than grow_full slots.  k_scan
+// takes the same decision from the same published line, so a round whose
+// scan was skipped is skipped too.
+__device__ __forceinline__ bool grid_too_small(const RoundArgs &a, const RoundState &rs) {
+  if (a.grow_list > 0 && !rs.scanned && rs.nlist > a.grow_list) return true;
+  return a.grow_full > 0 && a.mode != 1 && (rs.full || rs.scanned) && rs.n > a.grow_full;
 }
 
 // Publish round nx for the next launch (one thread).
@@ -1644,6 +1688,7 @@ __global__ void __launch_bounds__(1024) k_round(RoundArgs a) {
   int rr_local = r0 + 1;  // the round the next launch starts with
   int r_exec = rs.r;    // the last round this workgroup executed (phase trace)
   if (rs.done) return;
+  if (!rs.stop && grid_too_small(a, rs)) return;  // (every workgroup: same line)
   const int need0 = rs.need;
   if (wg >= need0) return;
   {
@@ -1779,6 +1824,7 @@ __global__ void __launch_bounds__(SCAN_BLOCK) k_scan(RoundArgs a) {
   const int flags = z.y;
   if (!(flags & PUB_SCAN_REQ) || (flags & (PUB_SCANNED | PUB_STOP))) return;
   const int r = x.y, n = x.w;
+  if (a.grow_full > 0 && n > a.grow_full) return;  // k_round skips the round too
   const unsigned e = (unsigned)(r & 1);
   const int S = a.scan_lists, lj = (int)blockIdx.x & (S - 1);
   int32_t *list = ((lj < 8) ? p.front0 : p.front1) + (int64_t)(lj & 7) * a.scan_rs;

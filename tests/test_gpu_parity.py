@@ -107,6 +107,24 @@ def test_ttree(mode):
 
 
 @pytest.mark.parametrize("mode", MODES)
+def test_fast_growing_term_resizes_the_grid(mode):
+    """A term that doubles every round (transformation tree of depth 15:
+    32768 leaves, each rewritten 26 times) starts on the grid sized for its
+    first node.  Rounds whose lists or sweep outgrow the grid are skipped by
+    the launches and the host captures a larger grid; the results are the
+    oracle's and the closed form's."""
+    w = G.ttree(15, pool_slots=1 << 20)
+    st = assert_parity(w.trs, w.terms, w.pool_slots, w.maxarity, label=f"{w.name} {mode} B64",
+                       mode=MODES[mode], block=64, nodes_per_thread=1)
+    assert st["rule_apps"] == CF.ttree_counts(15)
+    # every level's redexes share one numeral, whose reference count the
+    # firings update together (combined per wave): the 16 slots of the
+    # numeral S^15(0) die, no other slot does, so a lost or doubled
+    # decrement shows here
+    assert st["frees"] == 16
+
+
+@pytest.mark.parametrize("mode", MODES)
 def test_msort5_arity5(mode):
     trs = systems.msort5()
     rng = np.random.default_rng(5)
