@@ -59,6 +59,11 @@ def make_workload(name: str):
     if name.startswith("ttree"):
         d = int(name.split("_")[1]) if "_" in name else 22
         return G.ttree(d)
+    if name.startswith("tmsort"):
+        parts = name.split("_")[1:]
+        d = int(parts[0]) if parts else 23
+        k = int(parts[1]) if len(parts) > 1 else 5
+        return G.tmsort(d, k)
     raise SystemExit(f"unknown workload {name}")
 
 

@@ -125,6 +125,15 @@ def test_fast_growing_term_resizes_the_grid(mode):
 
 
 @pytest.mark.parametrize("mode", MODES)
+def test_tree_merge_sort(mode):
+    """The paper's tree merge sort (5-argument Merge2, maxarity 5): a tree of
+    depth 8 over 256 lists of 5 values, the generator the benchmark uses."""
+    w = G.tmsort(8, 5)
+    assert_parity(w.trs, w.terms, w.pool_slots, w.maxarity, label=f"{w.name} {mode}",
+                  mode=MODES[mode])
+
+
+@pytest.mark.parametrize("mode", MODES)
 def test_msort5_arity5(mode):
     trs = systems.msort5()
     rng = np.random.default_rng(5)

@@ -186,6 +186,37 @@ def test_ttree_closed_form(depth):
 
 # ------------------------------------------------------------------ paper's full merge sort
 
+def _list5(vs):
+    s = "Nil"
+    for v in reversed(vs):
+        s = f"Cons({'S(' * int(v)}Zero{')' * int(v)}, {s})"
+    return s
+
+
+def _tree5(lists, leaf="Leaf(Sort({}))"):
+    level = [leaf.format(_list5(v)) for v in lists]
+    while len(level) > 1:
+        level = [f"Node({level[i]}, {level[i + 1]})" for i in range(0, len(level), 2)]
+    return level[0]
+
+
+@pytest.mark.parametrize("depth,length", [(0, 5), (2, 3), (3, 5)])
+def test_tmsort_generator_matches_the_written_term(depth, length):
+    w = G.tmsort(depth, length)
+    vals = np.random.default_rng(G.BASE_SEED + 6).integers(0, 10, size=(1 << depth, length))
+    assert np.array_equal(w.terms[0], w.trs.encode(_tree5(vals)))
+    assert w.maxarity == 5
+
+
+def test_tmsort_normal_form_is_the_sorted_leaves():
+    # every leaf's list sorted by a host sort: the oracle's normal form of the
+    # tree, in the paper's own merge-sort system
+    w = G.tmsort(3, 5)
+    vals = np.random.default_rng(G.BASE_SEED + 6).integers(0, 10, size=(8, 5))
+    r = O.normalize(w.trs, w.terms[0])
+    want = w.trs.encode(_tree5([sorted(v) for v in vals], leaf="Leaf({})"))
+    assert np.array_equal(r.nf, want)
+
 def test_msort5_tree_of_lists():
     trs = systems.msort5()
     rng = np.random.default_rng(7)

@@ -22,6 +22,12 @@ contents the paper elides):
   with ``n`` uniform in 10..22; or ``sort`` of a list whose length is uniform in
   16..1024 with values uniform in 0..63.  Pool 2^27, maxarity 3.
 * cfg4 - cfg3 plus ``g(S^32(0))`` (4097 terms).  Pool 2^27, maxarity 3.
+* transformation tree of depth d - ``Expand(S^d(0))``.  Pool 2^26.
+* tree merge sort "d k" - one complete binary ``Node`` tree of depth d whose
+  2^d leaves are ``Leaf(Sort(list))`` of k numerals, values uniform in 0..9
+  (seed 7174 + 6), in the paper's own merge-sort system (``Merge2`` of arity
+  5).  Pool: the next power of two above four times the initial nodes, at
+  most 2^29.
 
 No function here rewrites, matches or evaluates a term.
 """
@@ -234,6 +240,44 @@ def ttree(depth: int = 22, pool_slots: int = 1 << 26) -> Workload:
     t = np.concatenate([[trs.sym_id["Expand"]], numeral(trs, depth)]).astype(np.int32)
     return Workload(f"ttree_{depth}", trs, [t], pool_slots, 2,
                     kinds=["ttree"], params=[{"depth": depth}])
+
+
+def tmsort(depth: int = 23, length: int = 5, seed: int = BASE_SEED + 6, vmax: int = 9,
+           pool_slots: int = 0) -> Workload:
+    """Tree merge sort: ``Node`` tree of depth ``depth`` over 2^depth leaves
+    ``Leaf(Sort(Cons(S^v1(Zero), ... Nil)))`` of ``length`` values each.
+
+    In prefix order leaf 0 follows ``depth`` Node symbols and leaf i > 0
+    follows as many as i has trailing zero bits (the subtrees it starts)."""
+    trs = systems.msort5()
+    sid = trs.sym_id
+    L = 1 << depth
+    vals = np.random.default_rng(seed).integers(0, vmax + 1, size=(L, length))
+    i = np.arange(L, dtype=np.int64)
+    k = np.zeros(L, dtype=np.int64)
+    k[0] = depth
+    low = i[1:] & -i[1:]                                   # lowest set bit
+    k[1:] = np.log2(low).astype(np.int64)
+    blk = vals + 2                                          # Cons, S^v, Zero
+    leaf_len = 3 + blk.sum(axis=1)                          # Leaf, Sort, ..., Nil
+    start = np.zeros(L, dtype=np.int64)
+    start[1:] = np.cumsum(k + leaf_len)[:-1]
+    total = int((k + leaf_len).sum())
+    out = np.full(total, sid["S"], dtype=np.int32)
+    run = np.repeat(np.cumsum(k) - k, k)
+    out[np.repeat(start, k) + np.arange(int(k.sum())) - run] = sid["Node"]
+    p = start + k
+    out[p] = sid["Leaf"]
+    out[p + 1] = sid["Sort"]
+    bstart = p[:, None] + 2 + np.concatenate(
+        [np.zeros((L, 1), np.int64), np.cumsum(blk, axis=1)[:, :-1]], axis=1)
+    out[bstart] = sid["Cons"]
+    out[bstart + 1 + vals] = sid["Zero"]
+    out[p + leaf_len - 1] = sid["Nil"]
+    if not pool_slots:  # (the library takes at most 2^29 slots)
+        pool_slots = 1 << min(29, max(20, int(math.ceil(math.log2(4 * total)))))
+    return Workload(f"tmsort_{depth}_{length}", trs, [out], pool_slots, 5,
+                    kinds=["tmsort"], params=[{"depth": depth, "length": length}])
 
 
 def cache_path() -> str:
