@@ -125,7 +125,7 @@ def test_fib_closed_form(n):
     np.testing.assert_array_equal(r.counts, CF.expect_counts(trs, CF.g_counts(n)))
 
 
-def test_fib_survey_totals():
+def test_fib_tabulated_totals():
     # totals from the recurrences G(n) = 1 + G(n-1) + G(n-2), P(n) = P(n-1) +
     # P(n-2) + Fib(n) + 1 (tabulated for the configurations)
     for n, total in [(20, 126681), (25, 1676377), (30, 21601675), (32, 59706401)]:
