@@ -84,9 +84,12 @@ typedef struct {
 #define TRS_MODE_PLAIN 0     /* full sweep of every slot every round */
 #define TRS_MODE_FRONTIER 1  /* sweep a compacted frontier; full confirmation
                                 sweep before declaring a normal form */
-#define TRS_MODE_LEARNED 2   /* frontier chosen by the trained predictor (below)
-                                instead of parent notification; full
-                                confirmation sweep as in TRS_MODE_FRONTIER */
+#define TRS_MODE_LEARNED 2   /* frontier: parent notification when an
+                                argument becomes a normal form, and for a
+                                node found blocked the trained predictor
+                                (below) decides whether it is examined again
+                                next round; full confirmation sweep as in
+                                TRS_MODE_FRONTIER */
 
 typedef struct {
   int32_t mode;              /* TRS_MODE_* */

@@ -27,8 +27,9 @@ struct RoundArgs {
   int32_t grow_list;
   int32_t grow_full;
   int32_t mode;         // 0 full sweeps, 1 frontier by parent notification,
-                        // 2 frontier chosen by the predictor (full sweep when
-                        // the frontier is empty)
+                        // 2 parent notification plus the predictor's choice
+                        // among blocked nodes (full sweep when the frontier
+                        // is empty)
   int32_t use_memo;     // memo shortcut on (off in learned mode and tracing)
   int32_t use_scan;     // plain mode: large full rounds are classified by k_scan
                         // (launched before each k_round) and run as list rounds

@@ -554,7 +554,7 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
       f = p.hss[s];
 #pragma unroll
       for (int j = 0; j < A; j++) raw[j] = p.args[(int64_t)s * A + j];
-      if (R.mode == 1) par_s = p.par[s];
+      if (R.mode != 0) par_s = p.par[s];
     }
     {
       if ((unsigned)f >= (unsigned)a.n_sym) {
@@ -617,7 +617,9 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
       const int fb = __builtin_ctz(~nfb) + 1;
       if (gate_keep(L, a.gate_off, f, nfb, bk)) {
         C.keep++;
-        qpush(L, L.qf, s, N);
+        // (through the notification stamp: an argument that became a
+        // normal form this round may queue the node too)
+        if (notify_parent(a, R, s)) qpush(L, L.qf, s, N);
         if (memo) p.state[s] = (uint8_t)ST_ACTIVE;
       } else if (fb != memo) {
         p.state[s] = (uint8_t)(ST_ACTIVE | (fb << ST_MEMO_SHIFT));
@@ -765,7 +767,7 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
       p.rc[slot] = rci;
       p.state[slot] = bnf ? (uint8_t)ST_NF : (uint8_t)(ST_ACTIVE | ST_PEND | (e << 2));
       if (track) p.lastchg[slot] = R.r;
-      if (R.mode <= 1) p.par[slot] = refr ? ns[refr - 1] : s;
+      p.par[slot] = refr ? ns[refr - 1] : s;
       if (frontier && !bnf) {
         bool keep = nready;
         if (!keep && R.mode == 2) {
@@ -821,7 +823,7 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
       p.hss[s] = sh;
       p.state[s] = pend_nf;
       if (track) p.lastchg[s] = R.r;
-      if (R.mode == 1) note = notify_parent(a, R, par_s);
+      if (R.mode != 0) note = notify_parent(a, R, par_s);
       if (R.mode == 0 && a.use_memo) wake_parent(a, R, s);
       if (frontier) qpush(L, L.qr, s, N);
     } else {
@@ -837,7 +839,7 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
       if (track) p.lastchg[s] = R.r;
       if (root_nf) {
         p.state[s] = pend_nf;
-        if (R.mode == 1) note = notify_parent(a, R, par_s);
+        if (R.mode != 0) note = notify_parent(a, R, par_s);
         if (R.mode == 0 && a.use_memo) wake_parent(a, R, s);
         if (frontier) qpush(L, L.qr, s, N);
       } else {
@@ -861,7 +863,9 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
             if (!keep)  // sleeps on its first argument not in normal form
               p.state[s] = (uint8_t)(ST_ACTIVE | ((__builtin_ctz(~bits) + 1) << ST_MEMO_SHIFT));
           }
-          if (keep) qpush(L, L.qf, s, N);
+          // (learned mode: through the notification stamp, which an argument
+          // that became a normal form this round may also take)
+          if (keep && (R.mode != 2 || notify_parent(a, R, s))) qpush(L, L.qf, s, N);
         }
       }
     }
@@ -916,7 +920,7 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
     C.nfset++;
     p.state[s] = pend_nf;
     if (track) p.lastchg[s] = R.r;
-    if (R.mode == 1) note = notify_parent(a, R, par_s);
+    if (R.mode != 0) note = notify_parent(a, R, par_s);
     if (R.mode == 0 && a.use_memo) wake_parent(a, R, s);
     if (frontier) qpush(L, L.qr, s, N);
   }
@@ -1306,7 +1310,7 @@ __device__ __forceinline__ void round_execute(const RoundArgs &a, Lds &L, const 
           pre.f = p.hss[x];
 #pragma unroll
           for (int j = 0; j < A; j++) pre.raw[j] = p.args[(int64_t)x * A + j];
-          pre.par = R.mode == 1 ? p.par[x] : 0;
+          pre.par = R.mode != 0 ? p.par[x] : 0;
           if ((st & ST_PEND) && ((st >> 2) & 1u) != R.e) {  // retire its own marker
             st = (st & ST_NF) ? ST_NF : ST_ACTIVE;
             p.state[x] = (uint8_t)st;
