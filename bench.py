@@ -228,6 +228,8 @@ def main():
                     help="comma-separated modes run once more for comparison ('' = none)")
     ap.add_argument("--weights", default=None, help="predictor parameters (.npz)")
     ap.add_argument("--threshold", type=float, default=0.1)
+    ap.add_argument("--sweep-every", type=int, default=0,
+                    help="learned mode: full sweep every k rounds (0 = library default)")
     ap.add_argument("--persistent", action="store_true")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--npt", type=int, default=0)
@@ -261,7 +263,7 @@ def main():
     if args.mode == "learned" or "learned" in compare:
         ctx.set_predictor(load_predictor(w, args.weights))
     opts = T.Options(block=args.block, nodes_per_thread=args.npt, mode=MODES[args.mode],
-                     persistent=1 if args.persistent else 0, threshold=args.threshold,
+                     persistent=1 if args.persistent else 0, threshold=args.threshold, sweep_every=args.sweep_every,
                      max_grid=args.max_grid, pf_depth=args.pf_depth)
     tune = None
     if not args.no_autotune and not args.block and not args.npt:
@@ -270,7 +272,8 @@ def main():
         # on the plain sweep for plain mode
         tmode = T.TRS_MODE_PLAIN if args.mode == "plain" else T.TRS_MODE_FRONTIER
         log(f"[bench] autotuning the launch shape (mode {tmode})")
-        tuned, tune = ctx.autotune(T.Options(mode=tmode, threshold=args.threshold))
+        tuned, tune = ctx.autotune(T.Options(mode=tmode, threshold=args.threshold,
+                                                    sweep_every=args.sweep_every))
         opts.block, opts.nodes_per_thread = tuned.block, tuned.nodes_per_thread
         opts.max_grid = tuned.max_grid
         log(f"[bench] autotune: {tune}")
@@ -348,7 +351,7 @@ def main():
         res["compare"] = {}
         for m in compare:
             o = T.Options(block=opts.block, nodes_per_thread=opts.nodes_per_thread, mode=MODES[m],
-                          persistent=1 if args.persistent else 0, threshold=args.threshold,
+                          persistent=1 if args.persistent else 0, threshold=args.threshold, sweep_every=args.sweep_every,
                           max_grid=opts.max_grid)
             if m == "plain" and tune is not None:
                 # the plain sweep has launch shapes of its own (full sweeps

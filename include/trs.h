@@ -113,9 +113,11 @@ typedef struct {
                                 fires or becomes a normal form within this
                                 many rounds (1 = the next round; 0 = 8) */
   int32_t sweep_every;       /* learned mode: also sweep every slot every k
-                                rounds, so that a node the predictor drops
-                                waits at most k rounds (0 = 8; -1 = only
-                                when the frontier is empty or a round stalls) */
+                                rounds (0 = 64; -1 = only when the frontier
+                                is empty or a round stalls); a node the
+                                predictor drops is woken by the notification
+                                of the argument it waits on, so these sweeps
+                                are a safety net */
   int32_t max_grid;          /* most workgroups a round launch uses (0 = 8 per
                                 compute unit); larger grids keep more sweep
                                 tiles in flight, smaller ones fewer idle
@@ -247,8 +249,9 @@ trs_status trs_membench(int32_t device, trs_membench_result *out);
  * network that predicts, for a node found blocked in a round (an argument
  * not yet a normal form), whether it will fire or become a normal form soon
  * (within the label horizon); only nodes it keeps are examined in the next
- * round, the others at the next full sweep (every sweep_every rounds), and a
- * full sweep still confirms the normal form (so results stay exact).
+ * round, the others when the argument they wait on becomes a normal form
+ * (parent notification) or at the next full sweep, and a full sweep still
+ * confirms the normal form (so results stay exact).
  *
  *   x  = [E[sym] (16), arity/8, c_0..c_4, bucket(age)/15, 0]       (24)
  *   h1 = relu(W1 x + b1) (32);  h2 = relu(W2 h1 + b2) (32)
