@@ -354,8 +354,8 @@ def main():
                           persistent=1 if args.persistent else 0, threshold=args.threshold, sweep_every=args.sweep_every,
                           max_grid=opts.max_grid)
             if m == "plain" and tune is not None:
-                # the plain sweep has launch shapes of its own (full sweeps
-                # every round: wide workgroups, about one per compute unit)
+                # the plain sweep has candidate shapes of its own (its round
+                # launch examines the scan kernel's lists)
                 log("[bench] autotuning the plain sweep's launch shape")
                 o, tune_m = ctx.autotune(o)
                 log(f"[bench] autotune plain: {tune_m}")
