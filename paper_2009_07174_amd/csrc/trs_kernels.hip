@@ -158,8 +158,10 @@ __device__ __forceinline__ int wave_reserve(bool pred, int32_t *ctr) {
 // serialise at about 8 ns each: millions of them per round without this.
 __device__ __forceinline__ int wave_combine(int t, int d) {
   const unsigned long long act = __ballot(1);
-  const int leader = __ffsll((long long)act) - 1;
-  const int tl = __shfl(t, leader, 64), dl = __shfl(d, leader, 64);
+  // (the leader is the same for the whole wave: a lane read, not an LDS
+  // permute, on the rewrite's dependent chain)
+  const int leader = __builtin_amdgcn_readfirstlane(__ffsll((long long)act) - 1);
+  const int tl = __builtin_amdgcn_readlane(t, leader), dl = __builtin_amdgcn_readlane(d, leader);
   const bool m = t == tl && d == dl;
   const unsigned long long same = __ballot(m);
   if (!m) return 1;
