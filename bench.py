@@ -22,7 +22,10 @@ outside the timed region).  The printed JSON line carries a
 ``roofline`` object for the round kernel (algorithmic bytes of the run /
 device time of the round loop, against 8 TB/s) and a ``cpu_baseline``
 object: the CPU oracle timed on a bounded sample of the same workload on one
-host core.
+host core.  The same CPU leg also runs the oracle on every term and compares
+its normal forms, element by element, and its per-rule counts with those read
+back from the device after each mode's run (``parity``); the script exits
+with status 3 when any differs.
 """
 
 from __future__ import annotations
@@ -217,6 +220,78 @@ def cpu_baseline_all_cores(w, budget_s: float = 15.0, max_threads: int = 16):
                       f"{state['apps']} rule applications, {wall:.2f} s wall on {cores} threads"}
 
 
+def host_cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def oracle_normal_forms(w, max_threads: int = 16):
+    """The oracle's normal forms and per-rule counts for every term of the
+    workload (untimed; a thread per host core over the independent terms,
+    each with an oracle of its own)."""
+    import threading
+    import numpy as np
+    from oracle import oracle as O
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    nt = max(1, min(cores, max_threads, w.n_terms))
+    nfs = [None] * w.n_terms
+    counts = [np.zeros(len(w.trs.rules), np.int64) for _ in range(nt)]
+    lock = threading.Lock()
+    nxt = {"i": 0}
+
+    def worker(k):
+        o = O.Oracle.from_trs(w.trs)
+        try:
+            while True:
+                with lock:
+                    i = nxt["i"]
+                    nxt["i"] = i + 1
+                if i >= w.n_terms:
+                    return
+                r = o.run(w.terms[i])
+                nfs[i] = r.nf
+                counts[k] += r.counts
+        finally:
+            o.close()
+
+    ts = [threading.Thread(target=worker, args=(k,)) for k in range(nt)]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    return nfs, np.sum(counts, axis=0)
+
+
+def parity_against_oracle(w, runs: dict) -> dict:
+    """Every mode's normal forms (read back from the device after its run)
+    compared element by element with the oracle's, and the per-rule counts."""
+    import numpy as np
+    t0 = time.perf_counter()
+    onfs, ocounts = oracle_normal_forms(w)
+    out = {"terms": w.n_terms, "compared": "canonical serialisation of every term, element by "
+                                           "element, and rule applications per rule",
+           "modes": {}}
+    for mode, (nfs, counts) in runs.items():
+        bad = [i for i in range(w.n_terms) if not np.array_equal(nfs[i], onfs[i])]
+        ok_counts = bool(np.array_equal(counts, ocounts))
+        out["modes"][mode] = {"ok": not bad and ok_counts, "differing_terms": len(bad),
+                              "first_differing_term": bad[0] if bad else None,
+                              "counts_equal": ok_counts}
+    out["ok"] = all(v["ok"] for v in out["modes"].values())
+    out["oracle_wall_s"] = time.perf_counter() - t0
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -296,6 +371,9 @@ def main():
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    # every normal form of the last timed step, read back through the C-ABI
+    # (checked against the oracle in the CPU leg below)
+    runs = {args.mode: ([ctx.read_nf(i) for i in range(w.n_terms)], ctx.rule_counts())}
     ev_ms = ev0.elapsed_time(ev1)
     ms_per_step = 1e3 * wall / args.steps
     st = stats[-1]
@@ -365,6 +443,7 @@ def main():
             torch.cuda.synchronize()
             wm = time.perf_counter() - t1
             log(f"[bench] compare {m}: {sm['rounds']} rounds, {sm['device_ms']:.1f} ms")
+            runs[m] = ([ctx.read_nf(i) for i in range(w.n_terms)], ctx.rule_counts())
             if sm["rule_apps"] != apps:
                 raise SystemExit(f"compare {m}: {sm['rule_apps']} rule applications, "
                                  f"expected {apps}")
@@ -399,14 +478,26 @@ def main():
         if "plain" in times:
             res["speedup_over_plain"] = {m: times["plain"] / t for m, t in times.items()
                                          if m != "plain"}
+    ctx.close()
+    parity_ok = True
     if not args.no_cpu_baseline:
+        # the CPU leg: the oracle timed on the host (cpu_baseline), and its
+        # normal forms compared with every mode's (parity)
+        cpu = host_cpu_model()
         log("[bench] CPU baseline (oracle, one core)")
         res["cpu_baseline"] = cpu_baseline(w)
+        res["cpu_baseline"]["cpu"] = cpu
         if w.n_terms > 1:  # independent terms: the oracle on every core as well
             log("[bench] CPU baseline (oracle, all cores)")
             res["cpu_baseline_all_cores"] = cpu_baseline_all_cores(w)
-    ctx.close()
+            res["cpu_baseline_all_cores"]["cpu"] = cpu
+        log("[bench] parity: every normal form against the oracle's")
+        res["parity"] = parity_against_oracle(w, runs)
+        parity_ok = res["parity"]["ok"]
+        log(f"[bench] parity: {res['parity']}")
     print(json.dumps(res))
+    if not parity_ok:
+        sys.exit(3)
 
 
 if __name__ == "__main__":

@@ -60,7 +60,8 @@ typedef int32_t trs_status;
 #define TRS_E_INTERNAL (-9)
 
 /* compiled-table limits (per rule / per system) */
-#define TRS_MAX_ARITY 8
+#define TRS_MAX_ARITY 5      /* highest symbol arity and highest maxarity the
+                               kernels are compiled for (TRS_E_LIMIT above) */
 #define TRS_MAX_PATTERN 8   /* left-hand-side nodes below the root */
 #define TRS_MAX_NEW 8       /* right-hand-side nodes created per rewrite */
 #define TRS_MAX_RULES 256
@@ -69,8 +70,9 @@ typedef int32_t trs_status;
 typedef struct trs_ctx trs_ctx;
 
 typedef struct {
-  int64_t pool_slots;  /* N: node slots in the pool (slot 0 is reserved) */
-  int32_t maxarity;    /* A: argument stride of the pool, 1..5;
+  int64_t pool_slots;  /* N: node slots in the pool, 2 .. 2^30 (slot 0 is
+                          reserved; indices are int32) */
+  int32_t maxarity;    /* A: argument stride of the pool, 1..TRS_MAX_ARITY;
                           0 = take the highest arity of the loaded system */
   int32_t device;      /* HIP device ordinal */
   void *hip_stream;    /* hipStream_t on which all device work is issued;
@@ -99,7 +101,10 @@ typedef struct {
                                 0 = tuned default */
   int32_t rounds_per_poll;   /* rounds issued between host checks of the
                                 device done flag; 0 = adaptive */
-  int64_t max_rounds;        /* 0 = unlimited; else TRS_E_ROUNDS past it */
+  int64_t max_rounds;        /* 0 = unlimited; else rounds 0..max_rounds-1 may
+                                run, and a run that has not reached its normal
+                                forms by then stops with TRS_E_ROUNDS (checked
+                                on the device at every round) */
   float threshold;           /* learned mode: keep a node when p >= threshold */
   int32_t persistent;        /* 1 = one cooperative persistent kernel runs the
                                 rounds with device-wide barriers; 0 = one
@@ -163,20 +168,47 @@ void trs_destroy(trs_ctx *ctx);
 trs_status trs_load_rules(trs_ctx *ctx, int32_t n_sym, const int32_t *arity, int32_t n_rules,
                           const int32_t *rule_off, const int32_t *rule_code, int64_t code_len);
 
-/* Load the ground input terms (prefix codes; term t occupies
- * term_code[term_off[t] .. term_off[t+1]) ).  Inputs are copied.  Every term
- * gets its own root entry; the terms share one node pool.  TRS_E_POOL if the
- * initial graph does not fit in pool_slots - 1 slots. */
+/* Load the ground input terms (Section 2: a term over the signature with no
+ * variables; its innermost normal form is what trs_normalize computes).
+ * term_code is the concatenation of the terms' prefix codes (pre-order symbol
+ * ids, int32); term t occupies term_code[term_off[t] .. term_off[t+1]) and
+ * term_off has n_terms + 1 entries.  Inputs are copied; the caller keeps
+ * ownership.  Each term is stored as a tree of nodes (one slot per symbol
+ * occurrence, Section 3's node arrays) with its own root entry, which holds
+ * one reference; all terms share one node pool.  Errors: TRS_E_STATE before
+ * trs_load_rules, TRS_E_ARG for null pointers or offsets outside code_len,
+ * TRS_E_TERM for an empty term, a variable (code < 0), an unknown symbol or
+ * a prefix code that does not parse, TRS_E_POOL if the initial graph does
+ * not fit in pool_slots - 1 slots.  A failed call leaves no terms loaded. */
 trs_status trs_load_terms(trs_ctx *ctx, int32_t n_terms, const int64_t *term_off,
                           const int32_t *term_code, int64_t code_len);
 
-/* Normalise all loaded terms on the device.  stats may be NULL.  On
- * TRS_E_POOL / TRS_E_ROUNDS the pool contents are unspecified and the terms
- * must be loaded again. */
+/* Normalise all loaded terms on the device: the round-synchronous innermost
+ * method of Section 3 (every node whose arguments are all normal forms is
+ * matched against its head symbol's rules in order and the first match is
+ * contracted in place; reference counts are adjusted and nodes whose count
+ * reaches zero are collected and their indices reused; rounds repeat until a
+ * round finds no node that is not a normal form).  The result is the
+ * innermost normal form of each term (Section 2, Definition 2 and the
+ * derive / rewrite_f procedures), identical whatever the mode and launch
+ * shape.  opts may be NULL (trs_default_opts); stats may be NULL.  Device
+ * work is issued on the context's stream and complete when the call
+ * returns.  Errors: TRS_E_STATE before trs_load_terms, TRS_E_ARG for option
+ * values outside their documented ranges, TRS_E_POOL when the pool runs out
+ * of slots, TRS_E_ROUNDS at opts->max_rounds, TRS_E_HIP for runtime errors
+ * (message in trs_last_error).  After an error the pool contents are
+ * unspecified; the next trs_normalize starts again from the loaded terms. */
 trs_status trs_normalize(trs_ctx *ctx, const trs_opts *opts, trs_stats *stats);
 
-/* Read back the normal form of term term_id as its canonical serialisation.
- * With buf == NULL only *len_out is set.  TRS_E_ARG if cap < length. */
+/* Read back the normal form of term term_id (0 .. n_terms-1) computed by the
+ * last successful trs_normalize, as its canonical serialisation: the prefix
+ * sequence of symbol ids of the term with every shared node expanded (the
+ * term itself of Section 2; sharing of Section 3 is not visible).  buf is
+ * caller-owned host memory of cap int32 entries; with buf == NULL only
+ * *len_out is set.  Errors: TRS_E_STATE before a successful trs_normalize,
+ * TRS_E_ARG for a bad term_id, a null len_out or cap < length,
+ * TRS_E_INTERNAL if the pool is inconsistent (a reachable node that is not a
+ * normal form or a dangling index). */
 trs_status trs_read_nf(trs_ctx *ctx, int32_t term_id, int32_t *buf, int64_t cap,
                        int64_t *len_out);
 

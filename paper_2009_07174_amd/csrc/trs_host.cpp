@@ -450,7 +450,8 @@ int default_npt() { return 16; }
 extern "C" {
 
 int64_t trs_device_bytes(int64_t pool_slots, int32_t maxarity) {
-  if (pool_slots < 2 || pool_slots > (1ll << 29) || maxarity < 1 || maxarity > 5) return -1;
+  if (pool_slots < 2 || pool_slots > (1ll << 30) || maxarity < 1 || maxarity > TRS_MAX_ARITY)
+    return -1;
   trs_ctx tmp;
   return (int64_t)carve_bytes(device_pieces(&tmp, pool_slots, maxarity));
 }
@@ -484,8 +485,8 @@ void trs_default_opts(trs_opts *o) {
 trs_status trs_create(trs_ctx **out, const trs_config *cfg) {
   if (!out || !cfg) return TRS_E_ARG;
   *out = nullptr;
-  if (cfg->pool_slots < 2 || cfg->pool_slots > (1ll << 29)) return TRS_E_ARG;
-  if (cfg->maxarity < 0 || cfg->maxarity > 5) return TRS_E_ARG;
+  if (cfg->pool_slots < 2 || cfg->pool_slots > (1ll << 30)) return TRS_E_ARG;
+  if (cfg->maxarity < 0 || cfg->maxarity > TRS_MAX_ARITY) return TRS_E_ARG;
   if (cfg->dev_mem && cfg->dev_bytes <= 0) return TRS_E_ARG;
   trs_ctx *c = new (std::nothrow) trs_ctx();
   if (!c) return TRS_E_INTERNAL;
@@ -521,14 +522,17 @@ trs_status trs_load_rules(trs_ctx *c, int32_t n_sym, const int32_t *arity, int32
   std::vector<int32_t> ar(arity, arity + n_sym);
   int maxar = 0;
   for (int i = 0; i < n_sym; i++) {
-    if (ar[i] < 0 || ar[i] > TRS_MAX_ARITY)
+    if (ar[i] < 0)
       return c->fail(TRS_E_RULE, "symbol " + std::to_string(i) + " has an invalid arity");
+    if (ar[i] > TRS_MAX_ARITY)
+      return c->fail(TRS_E_LIMIT, "symbol " + std::to_string(i) + ": arity above " +
+                                      std::to_string(TRS_MAX_ARITY) + " is not compiled");
     maxar = std::max(maxar, ar[i]);
   }
   int A = c->cfg.maxarity ? c->cfg.maxarity : std::max(1, maxar);
   if (maxar > A)
     return c->fail(TRS_E_RULE, "a symbol's arity exceeds maxarity " + std::to_string(A));
-  if (A > 5) return c->fail(TRS_E_LIMIT, "maxarity above 5 is not compiled");
+  if (A > TRS_MAX_ARITY) return c->fail(TRS_E_LIMIT, "maxarity above 5 is not compiled");
 
   std::vector<std::vector<PNode>> lhs(n_rules);
   std::vector<std::vector<RNode>> rhs(n_rules);
@@ -951,7 +955,8 @@ trs_status trs_normalize(trs_ctx *c, const trs_opts *opts_in, trs_stats *stats) 
     while (g < need) g <<= 1;
     return (int)std::min<int64_t>(g, std::min<int64_t>(512, 2 * (int64_t)std::max(1, c->cu_count)));
   };
-  ra.cont_rounds = o.max_rounds > 0 ? (int)std::min<int64_t>(o.max_rounds + 1, 4096) : 4096;
+  ra.cont_rounds = 4096;
+  ra.max_rounds = o.max_rounds;
   HIPCHK(c, hipEventRecord(c->ev0, s));
   const size_t small = offsetof(Ctl, stat);  // control words and round counters
   // opt-in progress lines on stderr for long runs (TRS_PROGRESS set)
@@ -1063,7 +1068,9 @@ trs_status trs_normalize(trs_ctx *c, const trs_opts *opts_in, trs_stats *stats) 
       break;
     }
     if (c->h_ctl->done) break;
-    if (o.max_rounds > 0 && r > o.max_rounds) {
+    // (the device stops the run at round max_rounds itself; this only guards
+    // a run whose device state is inconsistent)
+    if (o.max_rounds > 0 && r > o.max_rounds + 1) {
       result = c->fail(TRS_E_ROUNDS, "no normal form within max_rounds");
       break;
     }
@@ -1137,8 +1144,9 @@ trs_status trs_normalize(trs_ctx *c, const trs_opts *opts_in, trs_stats *stats) 
     c->trace_count = std::min<int64_t>(nt, tcap);
   }
   if (result == TRS_OK && h.err) {
-    result = c->fail(h.err, h.err == TRS_E_POOL ? "node pool exhausted during rewriting"
-                                                : "device reported an inconsistency");
+    result = c->fail(h.err, h.err == TRS_E_POOL     ? "node pool exhausted during rewriting"
+                            : h.err == TRS_E_ROUNDS ? "no normal form within max_rounds"
+                                                    : "device reported an inconsistency");
   }
   for (int i = 0; i < c->n_rules; i++) {
     unsigned long long t = 0;

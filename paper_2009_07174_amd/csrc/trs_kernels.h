@@ -18,6 +18,9 @@ struct RoundArgs {
   int32_t qbuf;         // LDS entries per thread of each list buffer
   int32_t nrounds;      // rounds a persistent launch may run
   int32_t cont_rounds;  // rounds workgroup 0 may continue alone in one launch
+  int64_t max_rounds;   // > 0: the run stops with TRS_E_ROUNDS before round
+                        // max_rounds would execute (rounds 0 .. max_rounds-1
+                        // may run); 0: unlimited
   int32_t small_cap;    // list items one workgroup takes on alone
   // a larger grid exists (0: the launch's grid is the largest): a launch
   // whose round lists more than grow_list items, or (plain and learned

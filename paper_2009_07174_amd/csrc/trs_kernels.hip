@@ -1048,6 +1048,12 @@ __device__ __forceinline__ RoundState round_state(const RoundArgs &a, int r) {
     stop = c_err != 0 || nn > p.N || (quiescent && c_dead == 0);
     err = c_err ? c_err : (nn > p.N ? -5 : 0);
   }
+  // the round limit (termination is undecidable, Section 2): a run that is
+  // not over by round max_rounds stops there with TRS_E_ROUNDS
+  if (!stop && a.max_rounds > 0 && r >= a.max_rounds) {
+    stop = true;
+    err = -6;
+  }
   if (quiescent) nfront = 0;
   rs.r = r;
   rs.n = n;

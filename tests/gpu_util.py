@@ -49,3 +49,56 @@ def assert_parity(trs, terms, pool_slots, maxarity=0, label="", predictor=None, 
     np.testing.assert_array_equal(counts, ocounts, err_msg=f"{label}: per-rule counts")
     assert st["rule_apps"] == int(ocounts.sum())
     return st
+
+
+def run_oracle_parallel(trs, terms, threads: int = 16):
+    """The oracle on every term of a batch (independent terms), a thread per
+    host core up to ``threads``, each with an oracle of its own; the C
+    library releases the interpreter lock while it normalises.  Returns
+    (normal forms in term order, per-rule counts summed over the batch)."""
+    import os
+    import threading
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    nt = max(1, min(threads, cores, len(terms)))
+    nfs = [None] * len(terms)
+    counts = [None] * nt
+    nxt = {"i": 0}
+    lock = threading.Lock()
+
+    def worker(k):
+        o = O.Oracle.from_trs(trs)
+        c = np.zeros(len(trs.rules), np.int64)
+        try:
+            while True:
+                with lock:
+                    i = nxt["i"]
+                    nxt["i"] = i + 1
+                if i >= len(terms):
+                    break
+                r = o.run(terms[i])
+                nfs[i] = r.nf
+                c += r.counts
+        finally:
+            o.close()
+            counts[k] = c
+
+    ts = [threading.Thread(target=worker, args=(k,)) for k in range(nt)]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    return nfs, np.sum(counts, axis=0)
+
+
+def compare_nfs(label, gpu_nfs, oracle_nfs):
+    """Element-wise comparison of the canonical serialisations."""
+    assert len(gpu_nfs) == len(oracle_nfs), label
+    bad = [i for i, (a, b) in enumerate(zip(gpu_nfs, oracle_nfs)) if not np.array_equal(a, b)]
+    if bad:
+        i = bad[0]
+        raise AssertionError(f"{label}: {len(bad)} of {len(gpu_nfs)} normal forms differ; first "
+                             f"term {i} (gpu length {len(gpu_nfs[i])}, oracle length "
+                             f"{len(oracle_nfs[i])})")

@@ -167,12 +167,21 @@ def test_pool_exhaustion_reports_error():
     assert e.value.code == T.TRS_E_POOL
 
 
-def test_round_limit_reports_error():
+@pytest.mark.parametrize("mode", MODES)
+def test_round_limit_reports_error(mode):
+    """f(a) -> f(f(a)) never ends: one new node per round, so a pool of 2^16
+    slots outlasts 200 rounds and the device's round limit must stop the
+    run with TRS_E_ROUNDS (and nothing else) after exactly 200 rounds."""
     from paper_2009_07174_amd import trs as T
     trs = parse_trs(systems.LOOP)
     with pytest.raises(T.TRSError) as e:
-        run_gpu(trs, [trs.encode("f(a)")], 1 << 16, max_rounds=200)
-    assert e.value.code in (T.TRS_E_ROUNDS, T.TRS_E_POOL)
+        run_gpu(trs, [trs.encode("f(a)")], 1 << 16, max_rounds=200, mode=MODES[mode])
+    assert e.value.code == T.TRS_E_ROUNDS
+    # a limit above the rounds a terminating run needs changes nothing
+    t = systems.fib()
+    nfs, _, st = run_gpu(t, [G.g_term(t, 12)], 1 << 16, max_rounds=100_000, mode=MODES[mode])
+    np.testing.assert_array_equal(nfs[0], CF.numeral_code(t, CF.fib(13)))
+    assert st["rounds"] < 100_000
 
 
 @pytest.mark.parametrize("mode", MODES)

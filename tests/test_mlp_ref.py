@@ -1,6 +1,8 @@
 """Pins for the CPU reference of the frontier predictor: central finite
 differences of its own loss, closed-form special cases, bfloat16 rounding."""
 
+import math
+
 import numpy as np
 import pytest
 
@@ -103,3 +105,53 @@ def test_decision_table_matches_forward():
     sym, bits, bucket = 2, 0b10101, 7
     p = M.forward_backward(params, [sym], [2], [bits], [bucket], [0])[1][0]
     assert tab[sym, bits, bucket] == pytest.approx(p, rel=1e-12)
+
+
+def test_forward_values_computed_by_hand():
+    """A two-symbol network with a few non-zero weights, evaluated by hand.
+
+    Record A: symbol 0 (E = [0.5, -1, 0...]), arity 2, argument bits 0b00101,
+    age bucket 3, label 1.  Record B: symbol 1 (E = [0, 0, 1.5, 0...]),
+    arity 1, bits 0b11110, bucket 0, label 0.  Inputs: x16 = arity/8,
+    x17..x21 = c_0..c_4, x22 = bucket/15.
+
+        h1_0 = relu(2 x0)                      A: 1      B: 0
+        h1_1 = relu(x1 + 0.5)                  A: 0      B: 0.5   (A: -0.5 cut)
+        h1_2 = relu(4 x16 + x17 + x19 - 0.5)   A: 2.5    B: 1
+        h1_3 = relu(5 x22)                     A: 1      B: 0
+        h1_4 = relu(x2 - 2 x18 + 0.25)         A: 0.25   B: 0     (B: -0.25 cut)
+        h2_0 = relu(h1_0 + h1_2 - 1)           A: 2.5    B: 0
+        h2_1 = relu(-h1_2 + 0.5)               A: 0      B: 0     (A: -2 cut)
+        h2_2 = relu(2 h1_3 + 4 h1_4)           A: 3      B: 0
+        h2_3 = relu(h1_1 + 3)                  A: 3      B: 3.5
+        z = h2_0 + 7 h2_1 - 0.5 h2_2 + 0.25 h2_3 - 1
+                                               A: 0.75   B: -0.125
+
+    A dropped ReLU, a missing bias, a transposed weight matrix or argument
+    bits read in the wrong order each change z."""
+    n_sym = 2
+    P = {k: np.zeros(s) for k, s in M.param_shapes(n_sym).items()}
+    P["E"][0, 0], P["E"][0, 1], P["E"][1, 2] = 0.5, -1.0, 1.5
+    W1, b1, W2, b2 = P["W1"], P["b1"], P["W2"], P["b2"]
+    W1[0, 0] = 2
+    W1[1, 1], b1[1] = 1, 0.5
+    W1[2, 16], W1[2, 17], W1[2, 19], b1[2] = 4, 1, 1, -0.5
+    W1[3, 22] = 5
+    W1[4, 2], W1[4, 18], b1[4] = 1, -2, 0.25
+    W2[0, 0], W2[0, 2], b2[0] = 1, 1, -1
+    W2[1, 2], b2[1] = -1, 0.5
+    W2[2, 3], W2[2, 4] = 2, 4
+    W2[3, 1], b2[3] = 1, 3
+    P["w3"][:4] = [1, 7, -0.5, 0.25]
+    P["b3"][0] = -1
+    # every weight is exactly representable in bfloat16
+    for v in P.values():
+        assert np.array_equal(M.bf16_round(v), v)
+    loss, p, _ = M.forward_backward(P, [0, 1], [2, 1], [0b00101, 0b11110], [3, 0], [1, 0])
+    zA, zB = 0.75, -0.125
+    sig = lambda z: 1.0 / (1.0 + math.exp(-z))
+    assert p[0] == pytest.approx(sig(zA), rel=1e-12)
+    assert p[1] == pytest.approx(sig(zB), rel=1e-12)
+    # binary cross-entropy: A (label 1) -log p_A, B (label 0) -log(1 - p_B)
+    want = 0.5 * (-math.log(sig(zA)) - math.log(1.0 - sig(zB)))
+    assert loss == pytest.approx(want, rel=1e-12)

@@ -27,7 +27,7 @@ contents the paper elides):
   2^d leaves are ``Leaf(Sort(list))`` of k numerals, values uniform in 0..9
   (seed 7174 + 6), in the paper's own merge-sort system (``Merge2`` of arity
   5).  Pool: the next power of two above four times the initial nodes, at
-  most 2^29.
+  most 2^30.
 
 No function here rewrites, matches or evaluates a term.
 """
@@ -274,8 +274,8 @@ def tmsort(depth: int = 23, length: int = 5, seed: int = BASE_SEED + 6, vmax: in
     out[bstart] = sid["Cons"]
     out[bstart + 1 + vals] = sid["Zero"]
     out[p + leaf_len - 1] = sid["Nil"]
-    if not pool_slots:  # (the library takes at most 2^29 slots)
-        pool_slots = 1 << min(29, max(20, int(math.ceil(math.log2(4 * total)))))
+    if not pool_slots:  # (the library takes at most 2^30 slots)
+        pool_slots = 1 << min(30, max(20, int(math.ceil(math.log2(4 * total)))))
     return Workload(f"tmsort_{depth}_{length}", trs, [out], pool_slots, 5,
                     kinds=["tmsort"], params=[{"depth": depth, "length": length}])
 
