@@ -351,6 +351,22 @@ trs_status trs_mlp_table(int32_t device, int32_t n_sym, const int32_t *arity,
                          const uint16_t *params_bf16, float threshold, float *probs_out,
                          uint32_t *words_out);
 
+/* trs_mlp_eval for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same computation, arguments and results as trs_mlp_eval (host arrays,
+ * copied in and out; work on the null stream, complete on return), with
+ * every device buffer -- parameters, records, gradient and loss
+ * accumulators, probabilities -- in a static device array of the library
+ * (about 0.8 MB per device, held until the process ends).  The call makes no
+ * hipMalloc or hipFree.  At most TRS_MLP_NOALLOC_MAX_RECORDS records per call
+ * (TRS_E_LIMIT above).  Calls on one device share that array: calls that
+ * overlap in time on the same device race and must be serialised by the
+ * caller. */
+#define TRS_MLP_NOALLOC_MAX_RECORDS 65536
+trs_status trs_mlp_eval_noalloc(int32_t device, int32_t n_sym, const uint16_t *params_bf16,
+                                int64_t n, const uint64_t *records, double *loss_out,
+                                float *grads_out, float *probs_out);
+
 /* Install predictor parameters in a context (copied; n_params must equal
  * trs_mlp_param_count of the loaded system).  Required before a
  * TRS_MODE_LEARNED trs_normalize. */

@@ -25,6 +25,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "trs.h"
@@ -328,6 +329,102 @@ out:
   (void)hipFree(dg);
   (void)hipFree(dl);
   (void)hipFree(dp);
+  return st;
+}
+
+// ------------------------------------------------------------------------
+// trs_mlp_eval_noalloc: trs_mlp_eval with every device buffer (parameters,
+// records, gradient and loss accumulators, probabilities) in one static
+// device array, so the call allocates nothing.  Each device holds its own
+// copy of the array until the process ends; its address on a device is taken
+// once, with that device current, by hipGetSymbolAddress, and only that
+// address is handed to kernels and copies (the array's name is a host-side
+// stand-in in host code).  Calls on one device share the array: calls that
+// overlap in time on one device race.
+#define NOALLOC_P_MAX 6144  // >= trs_mlp_param_count(TRS_MLP_MAX_SYM) = 5985
+constexpr size_t NA_OFF_W = 0;                                      // bfloat16 params
+constexpr size_t NA_OFF_G = NA_OFF_W + NOALLOC_P_MAX * 2;           // float gradient
+constexpr size_t NA_OFF_L = NA_OFF_G + NOALLOC_P_MAX * 4;           // float loss (256 B)
+constexpr size_t NA_OFF_R = NA_OFF_L + 256;                         // uint64 records
+constexpr size_t NA_OFF_P = NA_OFF_R + (size_t)TRS_MLP_NOALLOC_MAX_RECORDS * 8;  // float p
+constexpr size_t NA_BYTES = NA_OFF_P + (size_t)TRS_MLP_NOALLOC_MAX_RECORDS * 4;
+static_assert(NA_OFF_G % 256 == 0 && NA_OFF_L % 256 == 0 && NA_OFF_R % 256 == 0 &&
+                  NA_OFF_P % 256 == 0,
+              "scratch sections stay 256-byte aligned");
+
+static __device__ __align__(256) unsigned char scratch[NA_BYTES];
+
+namespace {
+
+#define NA_MAX_DEVICES 64
+std::mutex g_na_mutex;
+void *g_na_ptr[NA_MAX_DEVICES];  // device address of `scratch` per device (null: not yet)
+
+// The device address of this device's copy of `scratch` (the caller has made
+// `device` current); null on failure.
+void *noalloc_scratch(int device) {
+  std::lock_guard<std::mutex> lock(g_na_mutex);
+  if (!g_na_ptr[device]) {
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+    g_na_ptr[device] = ptr;
+  }
+  return g_na_ptr[device];
+}
+
+// Clears n floats (the accumulators must start at zero; a kernel rather than
+// a memset node).
+__global__ void k_zero_f32(float *p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.f;
+}
+
+}  // namespace
+
+extern "C" trs_status trs_mlp_eval_noalloc(int32_t device, int32_t n_sym,
+                                           const uint16_t *params_bf16, int64_t n,
+                                           const uint64_t *records, double *loss_out,
+                                           float *grads_out, float *probs_out) {
+  const int64_t P = trs_mlp_param_count(n_sym);
+  if (P < 0 || !params_bf16 || n <= 0 || !records || !loss_out) return TRS_E_ARG;
+  if (n > TRS_MLP_NOALLOC_MAX_RECORDS || P > NOALLOC_P_MAX) return TRS_E_LIMIT;
+  if (device < 0 || device >= NA_MAX_DEVICES) return TRS_E_ARG;
+  if (!records_valid(n_sym, n, records)) return TRS_E_ARG;
+  trs_status st = TRS_OK;
+  float hl = 0.f;
+  char *base = nullptr;
+  uint16_t *dw;
+  float *dg, *dl, *dp;
+  uint64_t *dr;
+  CK(hipSetDevice(device));
+  base = (char *)noalloc_scratch(device);
+  if (!base) return TRS_E_HIP;
+  dw = (uint16_t *)(base + NA_OFF_W);
+  dg = (float *)(base + NA_OFF_G);
+  dl = (float *)(base + NA_OFF_L);
+  dr = (uint64_t *)(base + NA_OFF_R);
+  dp = probs_out ? (float *)(base + NA_OFF_P) : nullptr;
+  CK(hipMemcpy(dw, params_bf16, P * 2, hipMemcpyHostToDevice));
+  CK(hipMemcpy(dr, records, n * 8, hipMemcpyHostToDevice));
+  // the previous call's gradient and loss are still there
+  hipLaunchKernelGGL(k_zero_f32, dim3((unsigned)((P + 1 + 255) / 256)), dim3(256), 0, 0, dg,
+                     (int)P);
+  hipLaunchKernelGGL(k_zero_f32, dim3(1), dim3(64), 0, 0, dl, 1);
+  CK(hipGetLastError());
+  {
+    const int64_t tiles = (n + T_TILE - 1) / T_TILE;
+    const int G = (int)(tiles < 1024 ? tiles : 1024);
+    hipLaunchKernelGGL(k_mlp_grad, dim3(G), dim3(NT), 0, 0, (const uint16_t *)dw, n_sym,
+                       (const uint64_t *)dr, (long long)n, 1.0f / (float)n, dg, dl, dp,
+                       grads_out ? 1 : 0);
+    CK(hipGetLastError());
+  }
+  CK(hipDeviceSynchronize());
+  CK(hipMemcpy(&hl, dl, 4, hipMemcpyDeviceToHost));
+  *loss_out = (double)hl / (double)n;
+  if (grads_out) CK(hipMemcpy(grads_out, dg, P * 4, hipMemcpyDeviceToHost));
+  if (probs_out) CK(hipMemcpy(probs_out, dp, n * 4, hipMemcpyDeviceToHost));
+out:
   return st;
 }
 

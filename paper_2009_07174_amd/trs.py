@@ -105,7 +105,7 @@ EXPORTS = ["trs_create", "trs_destroy", "trs_load_rules", "trs_load_terms", "trs
            "trs_read_nf", "trs_rule_counts", "trs_default_opts", "trs_device_bytes",
            "trs_membench", "trs_status_str", "trs_last_error", "trs_mlp_param_count",
            "trs_mlp_eval", "trs_mlp_train", "trs_mlp_table", "trs_set_predictor",
-           "trs_read_trace", "trs_autotune"]
+           "trs_read_trace", "trs_autotune", "trs_mlp_eval_noalloc"]
 
 
 def _load_lib():
@@ -155,6 +155,8 @@ def _load_lib():
     lib.trs_mlp_eval.argtypes = [ctypes.c_int32, ctypes.c_int32, u16p, ctypes.c_int64, u64p,
                                  P(ctypes.c_double), f32p, f32p]
     lib.trs_mlp_eval.restype = ctypes.c_int32
+    lib.trs_mlp_eval_noalloc.argtypes = lib.trs_mlp_eval.argtypes
+    lib.trs_mlp_eval_noalloc.restype = ctypes.c_int32
     lib.trs_mlp_train.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, u64p,
                                   P(trs_train_opts), u16p, u16p, P(trs_train_result)]
     lib.trs_mlp_train.restype = ctypes.c_int32
@@ -291,6 +293,28 @@ def trs_mlp_eval(n_sym: int, params_bf16, records, grads: bool = True, probs: bo
                            _ptr(p, ctypes.c_float) if probs else None)
     if st != TRS_OK:
         raise TRSError(st, "trs_mlp_eval")
+    return loss.value, g, p
+
+
+TRS_MLP_NOALLOC_MAX_RECORDS = 65536
+
+
+def trs_mlp_eval_noalloc(n_sym: int, params_bf16, records, grads: bool = True,
+                         probs: bool = False, device: int = 0):
+    """trs_mlp_eval computed in the library's static device buffer (the C
+    call allocates no device memory): (mean loss, gradients or None,
+    probabilities or None)."""
+    w, r = _u16(params_bf16), _u64(records)
+    P = trs_mlp_param_count(n_sym)
+    loss = ctypes.c_double(0.0)
+    g = np.zeros(max(P, 0), np.float32) if grads else None
+    p = np.zeros(len(r), np.float32) if probs else None
+    st = _lib.trs_mlp_eval_noalloc(device, n_sym, _ptr(w, ctypes.c_uint16), len(r),
+                                   _ptr(r, ctypes.c_uint64), ctypes.byref(loss),
+                                   _ptr(g, ctypes.c_float) if grads else None,
+                                   _ptr(p, ctypes.c_float) if probs else None)
+    if st != TRS_OK:
+        raise TRSError(st, "trs_mlp_eval_noalloc")
     return loss.value, g, p
 
 

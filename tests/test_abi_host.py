@@ -159,3 +159,18 @@ def test_normalize_without_gpu_reports_hip_error():
         c.normalize()
     assert e.value.code == T.TRS_E_HIP
     c.close()
+
+
+def test_noalloc_eval_rejects_oversized_batches_on_the_host():
+    # the size checks come before any device call
+    T = _lib()
+    n_sym = 3
+    P = T.trs_mlp_param_count(n_sym)
+    w = np.zeros(P, np.uint16)
+    rec = np.zeros(T.TRS_MLP_NOALLOC_MAX_RECORDS + 1, np.uint64)
+    with pytest.raises(T.TRSError) as e:
+        T.trs_mlp_eval_noalloc(n_sym, w, rec)
+    assert e.value.code == T.TRS_E_LIMIT
+    with pytest.raises(T.TRSError) as e:
+        T.trs_mlp_eval_noalloc(n_sym, w, rec[:0])
+    assert e.value.code == T.TRS_E_ARG
