@@ -299,7 +299,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cfg3")
     ap.add_argument("--mode", default="frontier", choices=["plain", "frontier", "learned"])
-    ap.add_argument("--compare", default="plain,learned",
+    ap.add_argument("--compare", default="plain,learned,frontier",
                     help="comma-separated modes run once more for comparison ('' = none)")
     ap.add_argument("--weights", default=None, help="predictor parameters (.npz)")
     ap.add_argument("--threshold", type=float, default=0.1)

@@ -118,11 +118,11 @@ typedef struct {
                                 fires or becomes a normal form within this
                                 many rounds (1 = the next round; 0 = 8) */
   int32_t sweep_every;       /* learned mode: also sweep every slot every k
-                                rounds (0 = 64; -1 = only when the frontier
-                                is empty or a round stalls); a node the
-                                predictor drops is woken by the notification
-                                of the argument it waits on, so these sweeps
-                                are a safety net */
+                                rounds (0 or -1 = never: only when the
+                                frontier is empty or a round stalls); a node
+                                the predictor drops is woken by the
+                                notification of the argument it waits on, so
+                                these sweeps are a safety net */
   int32_t max_grid;          /* most workgroups a round launch uses (0 = 8 per
                                 compute unit); larger grids keep more sweep
                                 tiles in flight, smaller ones fewer idle
@@ -131,6 +131,27 @@ typedef struct {
                                 workgroup copies ahead into LDS (1..4; 0 = as
                                 many as fit, at most 4; -1 = none, each tile
                                 read straight into registers) */
+  int32_t nf_walk;           /* frontier and learned modes, rounds that one
+                                workgroup runs alone: a node that becomes a
+                                normal form marks up to this many constructors
+                                above it (symbols without rules whose other
+                                arguments are normal forms) in the same
+                                round, walking up the parent hints; a longer
+                                chain goes on in the next round (0 = 256;
+                                -1 = off: one round per constructor) */
+  int32_t cont_passes;       /* frontier and learned modes with the walk on,
+                                rounds that one workgroup runs alone: a
+                                workgroup that creates a node ready at birth
+                                (all arguments normal forms), or rewrites one
+                                into a node that is ready again, examines it
+                                in a further pass of the same round rather
+                                than the next round, up to this many further
+                                passes per round (0 = 64; -1 = none) */
+  int32_t nf_walk_wide;      /* nf_walk for rounds that several workgroups
+                                run, where a walk holds up every term's round
+                                (0 = 1; -1 = off) */
+  int32_t cont_passes_wide;  /* cont_passes for rounds that several
+                                workgroups run (0 or -1 = none) */
 } trs_opts;
 
 typedef struct {
@@ -152,6 +173,8 @@ typedef struct {
                             recorded at their previous examination */
   int64_t mlp_kept;      /* learned mode: predictor decisions that kept the node */
   int64_t trace_records; /* trace records logged (may exceed trace_cap) */
+  int64_t nf_walked;     /* constructors marked normal forms by the walk of
+                            trs_opts.nf_walk (not counted in nf_set) */
   double device_ms;      /* device time of the round loop (HIP events) */
 } trs_stats;
 
@@ -211,6 +234,32 @@ trs_status trs_normalize(trs_ctx *ctx, const trs_opts *opts, trs_stats *stats);
  * normal form or a dangling index). */
 trs_status trs_read_nf(trs_ctx *ctx, int32_t term_id, int32_t *buf, int64_t cap,
                        int64_t *len_out);
+
+/* The node pool after the last successful trs_normalize, for checking the
+ * method's invariants from the host (Section 3: the node arrays, the
+ * reference counts and the free-index list that collection fills and
+ * allocation reuses).  info receives the slot extent n (slots 1..n-1 have
+ * been used; slot 0 never is), maxarity, the number of terms and the sizes
+ * of the two free-index stacks.  Each other pointer is caller-owned host
+ * memory, or NULL to skip that array: hss[n], args[n * maxarity]
+ * (maxarity-strided; entries past a symbol's arity unspecified), state[n]
+ * (bit 7: normal form; 0x00: free; bit 1 a round marker, bits 3-5 a memo),
+ * rc[n], free0[info.free0], free1[info.free1] (the free slot indices) and
+ * roots[n_terms] (the root slot of each term, which holds one reference).
+ * Call once with NULL arrays to learn the sizes.  Copies device memory;
+ * meant for tests and debugging, not for the hot path.  Errors:
+ * TRS_E_STATE before a successful trs_normalize, TRS_E_ARG for a null
+ * ctx or info, TRS_E_HIP for a failed copy. */
+typedef struct {
+  int64_t n;
+  int64_t free0, free1;
+  int32_t maxarity;
+  int32_t n_terms;
+} trs_pool_info;
+
+trs_status trs_read_pool(trs_ctx *ctx, trs_pool_info *info, int32_t *hss, int32_t *args,
+                         uint8_t *state, int32_t *rc, int32_t *free0, int32_t *free1,
+                         int32_t *roots);
 
 /* Rule applications per rule of the last trs_normalize (out[0..n_rules)). */
 trs_status trs_rule_counts(trs_ctx *ctx, int64_t *out, int32_t cap);

@@ -96,6 +96,7 @@ struct trs_ctx {
   // results of the last normalisation
   bool normalized = false;
   int64_t n_final = 0;
+  int64_t fs_final[2] = {0, 0};  // free-stack sizes at the end of the run
   std::vector<int64_t> rule_counts;
   bool cache_valid = false;
   std::vector<int32_t> c_hss, c_args;
@@ -343,6 +344,14 @@ trs_status compile_rule(int rid, const std::vector<int32_t> &arity,
   return TRS_OK;
 }
 
+// defaults of trs_opts.nf_walk, nf_walk_wide and cont_passes (frontier
+// modes): constructors one walk marks per round in rounds one workgroup runs
+// and in wider rounds, and further same-round passes in rounds one
+// workgroup runs (wider rounds run none unless cont_passes_wide asks)
+#define TRS_DEFAULT_WALK 256
+#define TRS_DEFAULT_WALK_WIDE 1
+#define TRS_DEFAULT_CONT 64
+
 #define HIPCHK(ctx, call)                                                              \
   do {                                                                                 \
     hipError_t e_ = (call);                                                            \
@@ -480,6 +489,10 @@ void trs_default_opts(trs_opts *o) {
   o->sweep_every = 0;
   o->max_grid = 0;
   o->pf_depth = 0;
+  o->nf_walk = 0;
+  o->cont_passes = 0;
+  o->nf_walk_wide = 0;
+  o->cont_passes_wide = 0;
 }
 
 trs_status trs_create(trs_ctx **out, const trs_config *cfg) {
@@ -709,6 +722,12 @@ trs_status trs_normalize(trs_ctx *c, const trs_opts *opts_in, trs_stats *stats) 
   if (o.max_grid < 0 || o.max_grid > (1 << 20))
     return c->fail(TRS_E_ARG, "max_grid must be 0..2^20");
   if (o.pf_depth < -1 || o.pf_depth > 4) return c->fail(TRS_E_ARG, "pf_depth must be -1..4");
+  if (o.nf_walk < -1 || o.nf_walk > (1 << 26) || o.nf_walk_wide < -1 ||
+      o.nf_walk_wide > (1 << 26))
+    return c->fail(TRS_E_ARG, "nf_walk and nf_walk_wide must be -1..2^26");
+  if (o.cont_passes < -1 || o.cont_passes > (1 << 20) || o.cont_passes_wide < -1 ||
+      o.cont_passes_wide > (1 << 20))
+    return c->fail(TRS_E_ARG, "cont_passes and cont_passes_wide must be -1..2^20");
   if (o.label_horizon < 0 || o.sweep_every < -1)
     return c->fail(TRS_E_ARG, "label_horizon must be >= 0, sweep_every >= -1");
   if (o.trace && o.mode != TRS_MODE_PLAIN)
@@ -843,10 +862,20 @@ trs_status trs_normalize(trs_ctx *c, const trs_opts *opts_in, trs_stats *stats) 
   ra.tab_words = gate_words ? gate_off + gate_words : (int32_t)c->tab.size();
   ra.gate_off = gate_off;
   ra.use_memo = o.trace ? 0 : 1;
-  // learned mode's periodic full sweeps: dropped nodes are woken by parent
-  // notification, so these only bound how long a missed wake-up could wait
-  // (on the 4096-term batch: 5.4 s every 8 rounds, 3.4 s every 64)
-  ra.sweep_every = o.mode == TRS_MODE_LEARNED ? (o.sweep_every == 0 ? 64 : std::max(0, o.sweep_every)) : 0;
+  // (0 = the default, -1 = off; the plain mode is the paper's one level per
+  // round)
+  auto opt = [](int32_t v, int32_t dflt) { return v == 0 ? dflt : std::max(0, v); };
+  const bool plain = o.mode == TRS_MODE_PLAIN;
+  ra.nf_walk = plain ? 0 : opt(o.nf_walk, TRS_DEFAULT_WALK);
+  ra.nf_walk_wide = plain ? 0 : opt(o.nf_walk_wide, TRS_DEFAULT_WALK_WIDE);
+  ra.cont_passes = ra.nf_walk ? opt(o.cont_passes, TRS_DEFAULT_CONT) : 0;
+  ra.cont_passes_wide = ra.nf_walk_wide ? std::max(0, o.cont_passes_wide) : 0;
+  // learned mode's periodic full sweeps (off by default): dropped nodes are
+  // woken by parent notification, and a round that makes no progress is
+  // followed by a full sweep, so these only bound how long a missed wake-up
+  // could wait (on the 4096-term batch, before the walk: 5.4 s every 8
+  // rounds, 3.4 s every 64)
+  ra.sweep_every = o.mode == TRS_MODE_LEARNED ? std::max(0, o.sweep_every) : 0;
   if (o.trace) {
     ra.label_h = o.label_horizon > 0 ? o.label_horizon : 8;
     ra.trace_rate = (uint32_t)o.trace;
@@ -1177,10 +1206,13 @@ trs_status trs_normalize(trs_ctx *c, const trs_opts *opts_in, trs_stats *stats) 
     stats->memo_blocked = sum(STAT_MEMO);
     stats->mlp_kept = sum(STAT_KEEP);
     stats->trace_records = sum(STAT_TRACE);
+    stats->nf_walked = sum(STAT_WALK);
     stats->device_ms = ms;
   }
   if (result != TRS_OK) return result;
   c->n_final = h.n_final;
+  c->fs_final[0] = h.fs_final[0];
+  c->fs_final[1] = h.fs_final[1];
   c->normalized = true;
   return TRS_OK;
 }
@@ -1316,6 +1348,35 @@ trs_status trs_read_trace(trs_ctx *c, uint64_t *buf, int64_t cap, int64_t *n_out
   if (k > 0)
     HIPCHK(c, hipMemcpy(buf, c->d_trace_rec, (size_t)k * 8, hipMemcpyDeviceToHost));
   *n_out = k;
+  return TRS_OK;
+}
+
+trs_status trs_read_pool(trs_ctx *c, trs_pool_info *info, int32_t *hss, int32_t *args,
+                         uint8_t *state, int32_t *rc, int32_t *free0, int32_t *free1,
+                         int32_t *roots) {
+  if (!c || !info) return TRS_E_ARG;
+  if (!c->normalized) return c->fail(TRS_E_STATE, "normalize first");
+  const int64_t n = c->n_final, A = c->A;
+  info->n = n;
+  info->maxarity = (int32_t)A;
+  info->n_terms = c->n_terms;
+  info->free0 = c->fs_final[0];
+  info->free1 = c->fs_final[1];
+  if (info->free0 < 0 || info->free1 < 0 || info->free0 > c->cfg.pool_slots ||
+      info->free1 > c->cfg.pool_slots)
+    return c->fail(TRS_E_INTERNAL, "free-stack sizes out of range");
+  const hipStream_t s = c->stream;
+  HIPCHK(c, hipStreamSynchronize(s));
+  if (hss) HIPCHK(c, hipMemcpy(hss, c->pool.hss, n * 4, hipMemcpyDeviceToHost));
+  if (args) HIPCHK(c, hipMemcpy(args, c->pool.args, n * A * 4, hipMemcpyDeviceToHost));
+  if (state) HIPCHK(c, hipMemcpy(state, c->pool.state, n, hipMemcpyDeviceToHost));
+  if (rc) HIPCHK(c, hipMemcpy(rc, c->pool.rc, n * 4, hipMemcpyDeviceToHost));
+  if (free0 && info->free0)
+    HIPCHK(c, hipMemcpy(free0, c->pool.fstack0, info->free0 * 4, hipMemcpyDeviceToHost));
+  if (free1 && info->free1)
+    HIPCHK(c, hipMemcpy(free1, c->pool.fstack1, info->free1 * 4, hipMemcpyDeviceToHost));
+  if (roots)
+    for (int32_t t = 0; t < c->n_terms; t++) roots[t] = c->roots[t];
   return TRS_OK;
 }
 

@@ -34,6 +34,14 @@ struct RoundArgs {
                         // among blocked nodes (full sweep when the frontier
                         // is empty)
   int32_t use_memo;     // memo shortcut on (off in learned mode and tracing)
+  int32_t nf_walk;      // frontier modes: most constructors above a node
+                        // that becomes a normal form that are marked in the
+                        // same round, in rounds one workgroup runs (0: none)
+  int32_t nf_walk_wide; // the same in rounds several workgroups run
+  int32_t cont_passes;  // further passes a workgroup may run in one list
+                        // round over the ready nodes it created or rewrote
+                        // in that round, in rounds one workgroup runs
+  int32_t cont_passes_wide;  // the same in rounds several workgroups run
   int32_t use_scan;     // plain mode: large full rounds are classified by k_scan
                         // (launched before each k_round) and run as list rounds
   int32_t round_block;  // k_round's block size (for the scan's hand-over)

@@ -229,6 +229,11 @@ struct Lds {
   // (entry scan_lists: their total)
   int32_t *soff;
   Queue qd, qf, qr;  // dead, frontier, retire
+  // same-round continuation (list rounds): two LDS buffers of ready nodes
+  // this workgroup created or rewrote, examined in further passes of the
+  // round (counts in misc[7] and misc[27]); cap entries each
+  int32_t *cb0, *cb1;
+  int ccap;
 };
 
 #define LSTAT_GC CTL_NSTAT
@@ -244,6 +249,17 @@ __device__ __forceinline__ void qpush(const Lds &L, const Queue &q, int32_t v, i
     int g = atomicAdd(q.gcount, 1);
     if (g < cap) q.out[g] = v;
   }
+}
+
+// Append a ready node to continuation buffer k (0 or 1); a full buffer
+// passes it on to the next round's frontier.
+__device__ __forceinline__ void qpush_cont(const Lds &L, int k, int32_t v, int64_t cap) {
+  int32_t *buf = k ? L.cb1 : L.cb0;
+  const int i = atomicAdd(&L.misc[k ? 27 : 7], 1);
+  if (i < L.ccap)
+    buf[i] = v;
+  else
+    qpush(L, L.qf, v, cap);
 }
 
 __device__ __forceinline__ void qreserve(const Lds &L, const Queue &q, int k) {
@@ -366,7 +382,7 @@ __device__ __forceinline__ void tflush(const RoundArgs &a, const Lds &L, int r) 
 }
 
 struct Counters {
-  int active, ready, fired, nfset, alloc, freed, rcops, memo, mlp, keep, trace;
+  int active, ready, fired, nfset, alloc, freed, rcops, memo, mlp, keep, trace, walk;
 };
 
 // Age bucket of the predictor's input: 0 for age 0, else
@@ -400,6 +416,11 @@ __device__ __forceinline__ void retire_marker(uint8_t *state, int s, unsigned ep
 
 struct RoundCtx {
   int r, n, fsP, mode;
+  bool walk;     // constructor walk (nf_walk) on in this round
+  int walk_max;  // constructors one walk may mark in this round
+  int cbuf;      // >= 0: ready nodes this thread creates or rewrites go to
+                 // continuation buffer cbuf (examined later in this round)
+  int cont;      // further passes this workgroup may run in this round
   unsigned e;
   int stamp;
   const int32_t *SP;
@@ -413,6 +434,106 @@ struct RoundCtx {
 __device__ __forceinline__ int notify_parent(const RoundArgs &a, const RoundCtx &R, int par) {
   if (par > 0 && par < a.p.N) return atomicExch(&a.p.qstamp[par], R.stamp) != R.stamp ? par : 0;
   return 0;
+}
+
+
+// Frontier rounds: node s has just become a normal form (with this round's
+// marker).  A symbol without rules over arguments that are all normal forms
+// is a normal form itself; rather than leaving each constructor above s to
+// a round of its own, the thread walks up the parent hints and marks such
+// ancestors normal forms in this round, at most R.walk_max of them, and
+// notifies the first node on the way that it does not mark (returned, as
+// notify_parent's result); a notified constructor over normal forms becomes
+// one next round and walks on from there.  The bound keeps a long chain
+// from holding up the round (a walk is one lane's sequence of dependent
+// reads, and the round ends with its longest walk).  This changes rounds
+// and visits only: no node is rewritten, so normal forms and rule
+// applications stay those of innermost rewriting.  (The term graph is
+// acyclic and each step checks that the parent references the node below
+// it, so a walk would end by itself.)
+//
+// An ancestor q is marked only when
+//   - q's live, without a marker and not a normal form, with a count above
+//     zero, and its symbol has no rules;
+//   - q was not queued for this round (its notification stamp is not the
+//     previous round's): no other thread examines it in this round, so no
+//     memo store can overwrite the mark (constructors reach a frontier only
+//     through that stamp);
+//   - the node below is one of q's arguments and every other argument is a
+//     normal form visible in this round.
+// q gets the plain normal-form state, without a marker: its fields were
+// written in earlier rounds and never change, so a parent examined later
+// in this round may read it at once.  Two walks that meet at a node both
+// stop there unless each sees the other's node marked; then both go on,
+// marking the same nodes with the same value.  Full rounds, where every
+// live slot is examined, notify only.
+// One level of the walk: a parent's fields and its own parent hint, loaded
+// together (the first level is loaded where the node becomes a normal form,
+// so that its latency overlaps the rewrite's reference-count atomics).
+template <int A>
+struct WalkLvl {
+  int par;  // 0: none
+  unsigned st;
+  int f, rc, qs, pp;
+  VecA<A> raw;
+};
+
+template <int A>
+__device__ __forceinline__ void walk_load(const Pool &p, int par, WalkLvl<A> &w) {
+  w.par = (par > 0 && par < p.N) ? par : 0;
+  if (!w.par) return;
+  w.st = p.state[par];
+  w.f = p.hss[par];
+  w.rc = p.rc[par];
+  w.qs = p.qstamp[par];
+  w.pp = p.par[par];
+#pragma unroll
+  for (int j = 0; j < A; j++) w.raw[j] = p.args[(int64_t)par * A + j];
+}
+
+template <int A>
+__device__ __forceinline__ int nf_walk(const RoundArgs &a, const Lds &L, const RoundCtx &R, int s,
+                                       WalkLvl<A> w, Counters &C) {
+  const Pool &p = a.p;
+  const int64_t N = p.N;
+  const bool track = R.mode == 2;  // keep lastchg
+  int cur = s;
+  for (int k = 0; k < R.walk_max; k++) {
+    if (!w.par) return 0;
+    const int par = w.par;
+    bool ok = (w.st & (ST_NF | ST_PEND | ST_ACTIVE)) == ST_ACTIVE && w.rc > 0 &&
+              w.qs != R.stamp - 1 && (unsigned)w.f < (unsigned)a.n_sym;
+    const int info = ok ? L.tab[TAB_SYM + w.f] : 0;
+    ok = ok && ((info >> 8) & 0xff) == 0;
+    const int ar = SYM_ARITY(info);
+    bool below = false;
+    if (ok) {
+      // (arity above one: the other arguments' states, one more step)
+      VecA<A> ost = (VecA<A>)(ST_NF);
+#pragma unroll
+      for (int j = 0; j < A; j++) {
+        if (j < ar) {
+          const int c = w.raw[j];
+          if (c == cur)
+            below = true;
+          else if ((unsigned)c < (unsigned)N && c > 0)
+            ost[j] = p.state[c];
+          else
+            ok = false;
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < A; j++)
+        if (j < ar && w.raw[j] != cur && !nf_visible((unsigned)ost[j], R.e)) ok = false;
+    }
+    if (!ok || !below) return notify_parent(a, R, par);
+    p.state[par] = (uint8_t)ST_NF;
+    if (track) p.lastchg[par] = R.r;
+    C.walk++;
+    cur = par;
+    walk_load<A>(p, w.pp, w);
+  }
+  return notify_parent(a, R, w.par);
 }
 
 typedef __attribute__((address_space(3))) void lds_void;
@@ -614,10 +735,14 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
     if (R.mode == 2) {
       // kept: examined next round (no memo, so a full sweep tests it in
       // full too); dropped: sleeps on its first blocking argument until a
-      // full sweep finds that argument in normal form
-      C.mlp++;
+      // full sweep finds that argument in normal form.  A symbol without
+      // rules can only become a normal form through its arguments, which
+      // notification (and the walk) report exactly, so such a node is not
+      // put to the predictor: it sleeps, and stays open to the walk.
       const int fb = __builtin_ctz(~nfb) + 1;
-      if (gate_keep(L, a.gate_off, f, nfb, bk)) {
+      const bool rules = ((info >> 8) & 0xff) != 0;
+      C.mlp += rules;
+      if (rules && gate_keep(L, a.gate_off, f, nfb, bk)) {
         C.keep++;
         // (through the notification stamp: an argument that became a
         // normal form this round may queue the node too)
@@ -743,6 +868,25 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
   }
   const uint8_t pend_nf = (uint8_t)(ST_NF | ST_PEND | (e << 2));
   int note = 0;  // parent to queue (frontier mode), once its exchange returns
+  bool walking = false;  // the slot became a normal form: walk up (nf_walk)
+  WalkLvl<A> wl;
+  wl.par = 0;
+  // The slot became a normal form in this round: its marker, then parent
+  // notification (frontier modes; with the walk, the walk's first level is
+  // loaded here, so that its latency overlaps the reference-count atomics)
+  // or the parent's wake bit (plain mode).
+  auto became_nf = [&]() {
+    p.state[s] = pend_nf;
+    if (track) p.lastchg[s] = R.r;
+    if (R.walk) {
+      walking = true;
+      walk_load<A>(p, par_s, wl);
+    } else if (R.mode != 0) {
+      note = notify_parent(a, R, par_s);
+    }
+    if (R.mode == 0 && a.use_memo) wake_parent(a, R, s);
+    if (frontier) qpush(L, L.qr, s, N);
+  };
   if (prog >= 0) {
     C.fired++;
     const int rsym = tab[prog + 1];
@@ -767,12 +911,18 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
       }
       p.hss[slot] = sym;
       p.rc[slot] = rci;
-      p.state[slot] = bnf ? (uint8_t)ST_NF : (uint8_t)(ST_ACTIVE | ST_PEND | (e << 2));
+      // (a round marker keeps a node created in a full round from the
+      // sweep of that round; in a list round with the walk, nothing but
+      // this thread's own lists reaches the new node, so it is plainly
+      // live and needs no retirement)
+      p.state[slot] = bnf      ? (uint8_t)ST_NF
+                      : R.walk ? (uint8_t)ST_ACTIVE
+                               : (uint8_t)(ST_ACTIVE | ST_PEND | (e << 2));
       if (track) p.lastchg[slot] = R.r;
       p.par[slot] = refr ? ns[refr - 1] : s;
       if (frontier && !bnf) {
         bool keep = nready;
-        if (!keep && R.mode == 2) {
+        if (!keep && R.mode == 2 && ((tab[TAB_SYM + sym] >> 8) & 0xff) != 0) {
           // its arguments: matched pattern nodes are normal forms (every
           // node below an innermost redex is), new ones by their born_nf flag
           int bits = 0;
@@ -789,10 +939,17 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
           keep = gate_keep(L, a.gate_off, sym, bits, 0);
           C.keep += keep;
         }
-        if (keep)
-          qpush(L, L.qf, slot, N);  // examined next round (retires its own marker)
-        else
+        if (keep) {
+          // (learned mode: a node the predictor keeps carries this round's
+          // notification stamp, like every other queued constructor)
+          if (!nready) p.qstamp[slot] = R.stamp;
+          if (nready && R.cbuf >= 0)
+            qpush_cont(L, R.cbuf, slot, N);  // examined later in this round
+          else
+            qpush(L, L.qf, slot, N);  // examined next round (retires its own marker)
+        } else if (!R.walk) {
           qpush(L, L.qr, slot, N);
+        }
       }
       bornmask |= bnf << j;
       q += 1 + ar2;
@@ -823,11 +980,7 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
         }
       }
       p.hss[s] = sh;
-      p.state[s] = pend_nf;
-      if (track) p.lastchg[s] = R.r;
-      if (R.mode != 0) note = notify_parent(a, R, par_s);
-      if (R.mode == 0 && a.use_memo) wake_parent(a, R, s);
-      if (frontier) qpush(L, L.qr, s, N);
+      became_nf();
     } else {
       const int rar = SYM_ARITY(tab[TAB_SYM + rsym]);
 #pragma unroll
@@ -840,15 +993,12 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
       p.hss[s] = rsym;
       if (track) p.lastchg[s] = R.r;
       if (root_nf) {
-        p.state[s] = pend_nf;
-        if (R.mode != 0) note = notify_parent(a, R, par_s);
-        if (R.mode == 0 && a.use_memo) wake_parent(a, R, s);
-        if (frontier) qpush(L, L.qr, s, N);
+        became_nf();
       } else {
         if (memo) p.state[s] = (uint8_t)ST_ACTIVE;  // the arguments changed: drop the memo
         if (frontier) {
           bool keep = root_ready;
-          if (!keep && R.mode == 2) {
+          if (!keep && R.mode == 2 && ((tab[TAB_SYM + rsym] >> 8) & 0xff) != 0) {
             int bits = 0;
 #pragma unroll
             for (int o = 0; o < 5; o++) {
@@ -867,7 +1017,10 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
           }
           // (learned mode: through the notification stamp, which an argument
           // that became a normal form this round may also take)
-          if (keep && (R.mode != 2 || notify_parent(a, R, s))) qpush(L, L.qf, s, N);
+          if (root_ready && R.cbuf >= 0)
+            qpush_cont(L, R.cbuf, s, N);  // ready again: examined later in this round
+          else if (keep && (R.mode != 2 || notify_parent(a, R, s)))
+            qpush(L, L.qf, s, N);
         }
       }
     }
@@ -920,12 +1073,9 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
     C.rcops += npos + nneg;
   } else if (nfset) {
     C.nfset++;
-    p.state[s] = pend_nf;
-    if (track) p.lastchg[s] = R.r;
-    if (R.mode != 0) note = notify_parent(a, R, par_s);
-    if (R.mode == 0 && a.use_memo) wake_parent(a, R, s);
-    if (frontier) qpush(L, L.qr, s, N);
+    became_nf();
   }
+  if (walking) note = nf_walk<A>(a, L, R, s, wl, C);
   if (note) qpush(L, L.qf, note, N);
   // per-rule counts: one LDS atomic per distinct rule among the wave's lanes
   // (every lane of the wave runs this loop; its trip count is uniform)
@@ -1215,6 +1365,8 @@ __device__ __forceinline__ void round_stop(const RoundArgs &a, const RoundState 
   ctl->done_round = rs.r;
   ctl->err = rs.err;
   ctl->n_final = rs.n;
+  ctl->fs_final[0] = rs.fs0;
+  ctl->fs_final[1] = rs.fs1;
 }
 
 // Execute round rs.r: bookkeeping by workgroup 0, then this workgroup's
@@ -1253,12 +1405,21 @@ __device__ __forceinline__ void round_execute(const RoundArgs &a, Lds &L, const 
   // strided over exactly those
   const int Ga = min(G, need);
   RoundCnt *cnt = &ctl->cnt[r3];
-  Counters C = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  Counters C = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   RoundCtx R;
   R.r = r;
   R.n = n;
   R.e = (unsigned)(r & 1);
   R.mode = mode;
+  // A walk or a further pass lengthens the round for every term, so rounds
+  // that several workgroups run (many terms or nodes at work) take the
+  // short settings, and rounds that one workgroup runs alone (a few chains
+  // left) the long ones.
+  const bool narrow = need == 1;
+  R.walk_max = narrow ? a.nf_walk : a.nf_walk_wide;
+  R.cont = narrow ? a.cont_passes : a.cont_passes_wide;
+  R.walk = R.walk_max > 0 && mode != 0 && !full && !quiescent;
+  R.cbuf = (R.walk && R.cont > 0) ? 0 : -1;
   R.cnt = cnt;
   R.stamp = rs.stamp + r;
   R.SP = (r & 1) ? p.fstack1 : p.fstack0;
@@ -1334,6 +1495,63 @@ __device__ __forceinline__ void round_execute(const RoundArgs &a, Lds &L, const 
       // (a scanned round's listed slots were counted as live by the scan)
       process_slot<A>(a, L, R, s, memo, rs.scanned, fslot, SQ, fsQ, C, pre);
     }
+  }
+
+  // ---- same-round continuation (list rounds with the walk): the ready
+  // nodes this workgroup created in the passes above (their arguments are
+  // normal forms visible in this round: matched nodes, or nodes born normal
+  // in the same rewrite), and the roots it rewrote that are ready again,
+  // are examined now instead of next round, pass after pass, while any are
+  // left and at most R.cont times.  Nothing outside this workgroup
+  // knows these nodes in this round (no list of the round holds them, and
+  // the walk never marks a node that has rules), so no other thread
+  // examines or writes them; the workgroup's own global writes of the last
+  // pass are complete and visible to all its waves after the barrier.
+  // Pass k examines buffer k mod 2 and appends to the other one; what is
+  // left when the passes run out goes to the next round's frontier.
+  if (R.cbuf >= 0) {
+    for (int pass = 0;; pass++) {
+      __syncthreads();
+      const int k = pass & 1;
+      int32_t *cb = k ? L.cb1 : L.cb0;
+      const int nc = min(L.misc[k ? 27 : 7], L.ccap);
+      if (nc == 0) break;
+      if (pass >= R.cont) {
+        // the rest: one reservation on the frontier, then the copy
+        if (tid == 0) L.misc[4] = atomicAdd(L.qf.gcount, nc);
+        __syncthreads();
+        const int gb = L.misc[4];
+        for (int i = tid; i < nc; i += B)
+          if ((int64_t)gb + i < p.N) L.qf.out[gb + i] = cb[i];
+        __syncthreads();
+        if (tid == 0) L.misc[k ? 27 : 7] = 0;
+        break;
+      }
+      R.cbuf = k ^ 1;
+      if (tid == 0) L.lstat[STAT_VISITS] += (unsigned long long)nc;
+      for (int b0 = 0; b0 < nc; b0 += B) {
+        const int i = b0 + tid;
+        int x = 0;
+        Pre<A> pre;
+        pre.have = false;
+        if (i < nc) {
+          const int v = cb[i];
+          if ((unsigned)v < (unsigned)p.N && v > 0) {
+            const unsigned st = p.state[v];
+            pre.have = true;
+            pre.f = p.hss[v];
+#pragma unroll
+            for (int j = 0; j < A; j++) pre.raw[j] = p.args[(int64_t)v * A + j];
+            pre.par = p.par[v];
+            if ((st & (ST_ACTIVE | ST_PEND | ST_NF)) == ST_ACTIVE) x = v;
+          }
+        }
+        process_slot<A>(a, L, R, x, 0, false, 0, SQ, fsQ, C, pre);
+      }
+      // (every thread read the count before the passes' barriers)
+      if (tid == 0) L.misc[k ? 27 : 7] = 0;
+    }
+    R.cbuf = 0;
   }
 
   tmark(a, L, r, 3);
@@ -1573,12 +1791,13 @@ __device__ __forceinline__ void round_execute(const RoundArgs &a, Lds &L, const 
     const int sn = wave_sum(C.nfset), sl = wave_sum(C.alloc), sd = wave_sum(C.freed);
     const int so = wave_sum(C.rcops), sm = wave_sum(C.memo);
     const int sp = wave_sum(C.mlp), sk = wave_sum(C.keep), st = wave_sum(C.trace);
+    const int sw = wave_sum(C.walk);
     if (lane() == 0) {
       if (sa) {
         L.misc[32] = 1;
         atomicAdd(&L.lstat[STAT_ACTIVE], (unsigned long long)sa);
       }
-      if (sf || sn) L.misc[33] = 1;
+      if (sf || sn || sw) L.misc[33] = 1;
       if (sr) atomicAdd(&L.lstat[STAT_READY], (unsigned long long)sr);
       if (sf) atomicAdd(&L.lstat[STAT_FIRED], (unsigned long long)sf);
       if (sn) atomicAdd(&L.lstat[STAT_NFSET], (unsigned long long)sn);
@@ -1589,6 +1808,7 @@ __device__ __forceinline__ void round_execute(const RoundArgs &a, Lds &L, const 
       if (sp) atomicAdd(&L.lstat[STAT_MLP], (unsigned long long)sp);
       if (sk) atomicAdd(&L.lstat[STAT_KEEP], (unsigned long long)sk);
       if (st) atomicAdd(&L.lstat[STAT_TRACE], (unsigned long long)st);
+      if (sw) atomicAdd(&L.lstat[STAT_WALK], (unsigned long long)sw);
     }
   }
   lds_sync();
@@ -1653,9 +1873,12 @@ __device__ __forceinline__ Lds setup_lds(const RoundArgs &a, int32_t *smem, bool
   L.qd.slot = 1;
   L.qf.slot = 2;
   L.qr.slot = 3;
-  L.pf = reinterpret_cast<uint4 *>(q + 3 * qc);
-  L.pfw = reinterpret_cast<uint32_t *>(q + 3 * qc + 4 * B * a.pf_depth);
-  L.misc = q + 3 * qc + 5 * B * a.pf_depth;
+  L.cb0 = q + 3 * qc;
+  L.cb1 = q + 4 * qc;
+  L.ccap = qc;
+  L.pf = reinterpret_cast<uint4 *>(q + 5 * qc);
+  L.pfw = reinterpret_cast<uint32_t *>(q + 5 * qc + 4 * B * a.pf_depth);
+  L.misc = q + 5 * qc + 5 * B * a.pf_depth;
   L.lstat = reinterpret_cast<unsigned long long *>(L.misc + 64);
   L.tstamp = reinterpret_cast<unsigned long long *>(L.misc + 64 + 2 * 16);
   L.soff = L.misc + 64 + 2 * 16 + 2 * TRACE_FIELDS;
@@ -1683,8 +1906,11 @@ __device__ __forceinline__ int bcast(const Lds &L, int v) {
 // of those rounds is its own, so no device-wide synchronisation is needed
 // and their working set stays in its XCD's L2.  The last workgroup to finish
 // advances ctl->r_cur past the last round executed.
-template <int A>
-__global__ void __launch_bounds__(1024) k_round(RoundArgs a) {
+// (compiled twice: for workgroups of up to 256 threads, which frontier and
+// list rounds use, the register budget is four times that of the
+// 1024-thread form, so the rewrite's values need not spill)
+template <int A, int MAXB>
+__global__ void __launch_bounds__(MAXB) k_round(RoundArgs a) {
   extern __shared__ int32_t smem[];
   Ctl *ctl = a.ctl;
   Lds L = setup_lds(a, smem, false);
@@ -2006,7 +2232,7 @@ __global__ void __launch_bounds__(1024) k_persistent(RoundArgs a) {
 size_t trs_round_lds_bytes(int block, int npt, int tab_words, int n_rules, int pf_depth,
                            int qbuf) {
   size_t words = (size_t)((tab_words + 3) & ~3) + (size_t)block * npt + block +
-                 (size_t)3 * qbuf * block + (size_t)5 * block * pf_depth + 64 + 2 * 16 +
+                 (size_t)5 * qbuf * block + (size_t)5 * block * pf_depth + 64 + 2 * 16 +
                  2 * TRACE_FIELDS + 32 + (size_t)n_rules;
   return words * sizeof(int32_t);
 }
@@ -2023,7 +2249,10 @@ size_t trs_round_lds_bytes(int block, int npt, int tab_words, int n_rules, int p
 
 template <int A>
 static void launch_round_A(const RoundArgs &a, int grid, int block, size_t lds, hipStream_t s) {
-  hipLaunchKernelGGL(k_round<A>, dim3(grid), dim3(block), lds, s, a);
+  if (block <= 256)
+    hipLaunchKernelGGL((k_round<A, 256>), dim3(grid), dim3(block), lds, s, a);
+  else
+    hipLaunchKernelGGL((k_round<A, 1024>), dim3(grid), dim3(block), lds, s, a);
 }
 
 static hipError_t g_coop_status = hipSuccess;
@@ -2042,8 +2271,10 @@ static void occ_A(int *out, int block, size_t lds) {
 
 template <int A>
 static void set_attr_A(size_t lds) {
-  (void)hipFuncSetAttribute((const void *)k_round<A>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)lds);
+  (void)hipFuncSetAttribute((const void *)k_round<A, 256>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  (void)hipFuncSetAttribute((const void *)k_round<A, 1024>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   (void)hipFuncSetAttribute((const void *)k_persistent<A>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }

@@ -83,7 +83,7 @@ static inline int32_t tab_sym_word(int32_t arity, int32_t nrules, int32_t first,
 #define CTL_SPREAD 64    // statistics counters are spread over this many words
 #define RULE_SPREAD 16   // per-rule counters are spread over this many copies
 #define TICKET_GROUPS 64
-#define CTL_NSTAT 12
+#define CTL_NSTAT 13
 enum {
   STAT_ACTIVE = 0,  // live non-normal-form slots visited
   STAT_READY,       // of those, all arguments in normal form
@@ -97,6 +97,8 @@ enum {
   STAT_MEMO,        // active slots found still blocked by their memo argument
   STAT_KEEP,        // predictor decisions that kept the node
   STAT_TRACE,       // trace records logged (including ones past the cap)
+  STAT_WALK,        // constructors marked normal forms by a walk up the
+                    // parent hints in the round their last argument did
 };
 
 // Each counter on a 128-byte line of its own: atomics to one line
@@ -140,7 +142,8 @@ struct Ctl {
   int32_t stamp_base;  // frontier-notification stamps of this run start here
   int32_t full_sweeps; // rounds that swept every slot
   int32_t r_reached;   // round after the last one workgroup 0 ran alone
-  int32_t pad2[4];
+  int32_t fs_final[2]; // free-stack sizes when the run ended
+  int32_t pad2[2];
   alignas(128) RoundCnt cnt[3];  // counters accumulated during round r (index r % 3)
   // state of the next launch's first round, published by the last workgroup
   // of a launch (the host writes it for round 0): done, r, need, n, fs0, fs1,

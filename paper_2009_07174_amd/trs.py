@@ -40,14 +40,16 @@ class trs_opts(ctypes.Structure):
                 ("persistent", ctypes.c_int32), ("trace", ctypes.c_int32),
                 ("trace_cap", ctypes.c_int64), ("label_horizon", ctypes.c_int32),
                 ("sweep_every", ctypes.c_int32), ("max_grid", ctypes.c_int32),
-                ("pf_depth", ctypes.c_int32)]
+                ("pf_depth", ctypes.c_int32), ("nf_walk", ctypes.c_int32),
+                ("cont_passes", ctypes.c_int32), ("nf_walk_wide", ctypes.c_int32),
+                ("cont_passes_wide", ctypes.c_int32)]
 
 
 class trs_stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in (
         "rounds", "rule_apps", "node_visits", "active_visits", "allocs", "frees",
         "peak_slots", "gc_rounds", "mlp_evals", "full_sweeps", "launches", "ready_visits",
-        "nf_set", "rc_atomics", "memo_blocked", "mlp_kept", "trace_records")] + [
+        "nf_set", "rc_atomics", "memo_blocked", "mlp_kept", "trace_records", "nf_walked")] + [
         ("device_ms", ctypes.c_double)]
 
     def as_dict(self):
@@ -99,13 +101,18 @@ class trs_tune_result(ctypes.Structure):
                           for i in range(k)]}
 
 
+class trs_pool_info(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("free0", ctypes.c_int64), ("free1", ctypes.c_int64),
+                ("maxarity", ctypes.c_int32), ("n_terms", ctypes.c_int32)]
+
+
 TRS_MLP_EMB, TRS_MLP_DIN, TRS_MLP_H, TRS_MLP_MAX_SYM = 16, 24, 32, 256
 
 EXPORTS = ["trs_create", "trs_destroy", "trs_load_rules", "trs_load_terms", "trs_normalize",
            "trs_read_nf", "trs_rule_counts", "trs_default_opts", "trs_device_bytes",
            "trs_membench", "trs_status_str", "trs_last_error", "trs_mlp_param_count",
            "trs_mlp_eval", "trs_mlp_train", "trs_mlp_table", "trs_set_predictor",
-           "trs_read_trace", "trs_autotune", "trs_mlp_eval_noalloc"]
+           "trs_read_trace", "trs_autotune", "trs_mlp_eval_noalloc", "trs_read_pool"]
 
 
 def _load_lib():
@@ -138,6 +145,9 @@ def _load_lib():
     lib.trs_read_nf.restype = ctypes.c_int32
     lib.trs_rule_counts.argtypes = [vp, i64p, ctypes.c_int32]
     lib.trs_rule_counts.restype = ctypes.c_int32
+    lib.trs_read_pool.argtypes = [vp, P(trs_pool_info), i32p, i32p, P(ctypes.c_uint8), i32p,
+                                  i32p, i32p, i32p]
+    lib.trs_read_pool.restype = ctypes.c_int32
     lib.trs_default_opts.argtypes = [P(trs_opts)]
     lib.trs_default_opts.restype = None
     lib.trs_device_bytes.argtypes = [ctypes.c_int64, ctypes.c_int32]
@@ -249,6 +259,30 @@ def trs_rule_counts(h, n_rules: int) -> np.ndarray:
     _check(h, _lib.trs_rule_counts(h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                                    len(out)))
     return out[:n_rules]
+
+
+def trs_read_pool(h) -> dict:
+    """The node pool after the last normalisation (hss, args as an n x A
+    array, state, rc, the two free stacks' entries, the term roots)."""
+    info = trs_pool_info()
+    nul = ctypes.POINTER(ctypes.c_int32)()
+    _check(h, _lib.trs_read_pool(h, ctypes.byref(info), nul, nul,
+                                 ctypes.POINTER(ctypes.c_uint8)(), nul, nul, nul, nul))
+    n, A = int(info.n), int(info.maxarity)
+    hss = np.zeros(max(n, 1), np.int32)
+    args = np.zeros(max(n * A, 1), np.int32)
+    state = np.zeros(max(n, 1), np.uint8)
+    rc = np.zeros(max(n, 1), np.int32)
+    f0 = np.zeros(max(int(info.free0), 1), np.int32)
+    f1 = np.zeros(max(int(info.free1), 1), np.int32)
+    roots = np.zeros(max(int(info.n_terms), 1), np.int32)
+    ip = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))  # noqa: E731
+    _check(h, _lib.trs_read_pool(h, ctypes.byref(info), ip(hss), ip(args),
+                                 state.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), ip(rc),
+                                 ip(f0), ip(f1), ip(roots)))
+    return {"n": n, "maxarity": A, "hss": hss[:n], "args": args[:n * A].reshape(n, A),
+            "state": state[:n], "rc": rc[:n], "free0": f0[:int(info.free0)],
+            "free1": f1[:int(info.free1)], "roots": roots[:int(info.n_terms)]}
 
 
 def trs_membench(device: int = 0) -> dict:
@@ -385,12 +419,17 @@ class Options:
     sweep_every: int = 0
     max_grid: int = 0
     pf_depth: int = 0
+    nf_walk: int = 0
+    cont_passes: int = 0
+    nf_walk_wide: int = 0
+    cont_passes_wide: int = 0
 
     def to_c(self) -> trs_opts:
         o = trs_default_opts()
         for k in ("mode", "block", "nodes_per_thread", "rounds_per_poll", "max_rounds",
                   "threshold", "persistent", "trace", "trace_cap", "label_horizon",
-                  "sweep_every", "max_grid", "pf_depth"):
+                  "sweep_every", "max_grid", "pf_depth", "nf_walk", "cont_passes",
+                  "nf_walk_wide", "cont_passes_wide"):
             setattr(o, k, getattr(self, k))
         return o
 
@@ -477,6 +516,9 @@ class Context:
 
     def rule_counts(self) -> np.ndarray:
         return trs_rule_counts(self.h, self.n_rules)
+
+    def read_pool(self) -> dict:
+        return trs_read_pool(self.h)
 
     def set_predictor(self, params_bf16):
         trs_set_predictor(self.h, params_bf16)

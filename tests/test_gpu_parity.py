@@ -30,7 +30,12 @@ def test_golden(path):
     assert_parity(trs, [trs.encode(ex["input"])], 1 << 12, label=os.path.basename(path))
 
 
-MODES = {"plain": 0, "frontier": 1}
+# option sets: the plain sweep, the parent-notification frontier (with the
+# constructor walk and same-round continuation, its defaults), the frontier
+# without either, and the frontier with the walk but no continuation
+MODES = {"plain": dict(mode=0), "frontier": dict(mode=1),
+         "frontier_nowalk": dict(mode=1, nf_walk=-1, nf_walk_wide=-1),
+         "frontier_nocont": dict(mode=1, cont_passes=-1)}
 
 
 @pytest.mark.parametrize("mode", MODES)
@@ -38,14 +43,14 @@ def test_peano_small_trees(mode):
     trs = systems.peano()
     rng = np.random.default_rng(11)
     terms = [G.peano_tree(trs, rng, int(rng.integers(1, 300))) for _ in range(24)]
-    assert_parity(trs, terms, 1 << 18, label=f"peano small {mode}", mode=MODES[mode])
+    assert_parity(trs, terms, 1 << 18, label=f"peano small {mode}", **MODES[mode])
 
 
 @pytest.mark.parametrize("mode", MODES)
 def test_cfg0(mode):
     w = G.cfg0()
     st = assert_parity(w.trs, w.terms, w.pool_slots, w.maxarity, label=f"{w.name} {mode}",
-                       mode=MODES[mode])
+                       **MODES[mode])
     v, cnt = CF.peano_eval(w.trs, w.terms[0])
     assert st["rule_apps"] == sum(cnt.values())
 
@@ -54,7 +59,7 @@ def test_cfg0(mode):
 @pytest.mark.parametrize("n", [0, 1, 2, 3, 7, 12, 16])
 def test_fib_small(n, mode):
     trs = systems.fib()
-    assert_parity(trs, [G.g_term(trs, n)], 1 << 16, label=f"g({n}) {mode}", mode=MODES[mode])
+    assert_parity(trs, [G.g_term(trs, n)], 1 << 16, label=f"g({n}) {mode}", **MODES[mode])
 
 
 @pytest.mark.parametrize("mode", MODES)
@@ -62,7 +67,7 @@ def test_fib_small(n, mode):
 def test_cfg1(n, mode):
     w = G.cfg1(n)
     st = assert_parity(w.trs, w.terms, w.pool_slots, w.maxarity, label=f"{w.name} {mode}",
-                       mode=MODES[mode])
+                       **MODES[mode])
     assert st["rule_apps"] == sum(CF.g_counts(n).values())
 
 
@@ -72,21 +77,21 @@ def test_msort_small_lists(mode):
     rng = np.random.default_rng(12)
     terms = [G.sort_term(trs, rng.integers(0, 64, size=int(rng.integers(0, 70))))
              for _ in range(16)]
-    assert_parity(trs, terms, 1 << 20, label=f"msort small {mode}", mode=MODES[mode])
+    assert_parity(trs, terms, 1 << 20, label=f"msort small {mode}", **MODES[mode])
 
 
 @pytest.mark.parametrize("mode", MODES)
 def test_cfg2(mode):
     w = G.cfg2()
     assert_parity(w.trs, w.terms, w.pool_slots, w.maxarity, label=f"{w.name} {mode}",
-                  mode=MODES[mode])
+                  **MODES[mode])
 
 
 @pytest.mark.parametrize("mode", MODES)
 def test_batch_mini(mode):
     w = G.cfg3(n_terms=96, pool_slots=1 << 22, scale="mini")
     assert_parity(w.trs, w.terms, w.pool_slots, w.maxarity, label=f"{w.name} {mode}",
-                  mode=MODES[mode])
+                  **MODES[mode])
 
 
 @pytest.mark.parametrize("mode", MODES)
@@ -95,14 +100,14 @@ def test_launch_shapes_agree(block, npt, mode):
     w = G.cfg3(n_terms=48, pool_slots=1 << 21, scale="mini")
     assert_parity(w.trs, w.terms, w.pool_slots, w.maxarity,
                   label=f"mini B{block} npt{npt} {mode}", block=block, nodes_per_thread=npt,
-                  mode=MODES[mode])
+                  **MODES[mode])
 
 
 @pytest.mark.parametrize("mode", MODES)
 def test_ttree(mode):
     w = G.ttree(10, pool_slots=1 << 18)
     st = assert_parity(w.trs, w.terms, w.pool_slots, w.maxarity, label=f"{w.name} {mode}",
-                       mode=MODES[mode])
+                       **MODES[mode])
     assert st["rule_apps"] == CF.ttree_counts(10)
 
 
@@ -115,7 +120,7 @@ def test_fast_growing_term_resizes_the_grid(mode):
     oracle's and the closed form's."""
     w = G.ttree(15, pool_slots=1 << 20)
     st = assert_parity(w.trs, w.terms, w.pool_slots, w.maxarity, label=f"{w.name} {mode} B64",
-                       mode=MODES[mode], block=64, nodes_per_thread=1)
+                       **MODES[mode], block=64, nodes_per_thread=1)
     assert st["rule_apps"] == CF.ttree_counts(15)
     # every level's redexes share one numeral, whose reference count the
     # firings update together (combined per wave): the 16 slots of the
@@ -130,7 +135,7 @@ def test_tree_merge_sort(mode):
     depth 8 over 256 lists of 5 values, the generator the benchmark uses."""
     w = G.tmsort(8, 5)
     assert_parity(w.trs, w.terms, w.pool_slots, w.maxarity, label=f"{w.name} {mode}",
-                  mode=MODES[mode])
+                  **MODES[mode])
 
 
 @pytest.mark.parametrize("mode", MODES)
@@ -147,7 +152,7 @@ def test_msort5_arity5(mode):
     for _ in range(6):
         leaves = [f"Leaf(Sort({lst(rng.integers(0, 9, size=7))}))" for _ in range(4)]
         terms.append(trs.encode(f"Node(Node({leaves[0]}, {leaves[1]}), Node({leaves[2]}, {leaves[3]}))"))
-    assert_parity(trs, terms, 1 << 16, label=f"msort5 {mode}", mode=MODES[mode])
+    assert_parity(trs, terms, 1 << 16, label=f"msort5 {mode}", **MODES[mode])
 
 
 def test_already_normal_and_empty():
@@ -175,11 +180,11 @@ def test_round_limit_reports_error(mode):
     from paper_2009_07174_amd import trs as T
     trs = parse_trs(systems.LOOP)
     with pytest.raises(T.TRSError) as e:
-        run_gpu(trs, [trs.encode("f(a)")], 1 << 16, max_rounds=200, mode=MODES[mode])
+        run_gpu(trs, [trs.encode("f(a)")], 1 << 16, max_rounds=200, **MODES[mode])
     assert e.value.code == T.TRS_E_ROUNDS
     # a limit above the rounds a terminating run needs changes nothing
     t = systems.fib()
-    nfs, _, st = run_gpu(t, [G.g_term(t, 12)], 1 << 16, max_rounds=100_000, mode=MODES[mode])
+    nfs, _, st = run_gpu(t, [G.g_term(t, 12)], 1 << 16, max_rounds=100_000, **MODES[mode])
     np.testing.assert_array_equal(nfs[0], CF.numeral_code(t, CF.fib(13)))
     assert st["rounds"] < 100_000
 
@@ -188,7 +193,7 @@ def test_round_limit_reports_error(mode):
 def test_persistent_kernel_agrees(mode):
     w = G.cfg3(n_terms=48, pool_slots=1 << 21, scale="mini")
     assert_parity(w.trs, w.terms, w.pool_slots, w.maxarity, label=f"mini persistent {mode}",
-                  persistent=1, mode=MODES[mode])
+                  persistent=1, **MODES[mode])
 
 
 def test_frontier_with_shared_redexes():
@@ -210,7 +215,7 @@ eqn p(S(X), Y) = S(p(X, Y))
         ks = (0, 1, 3, 6)
         terms = [trs.encode("d(" + "S(" * k + "0" + ")" * k + ")") for k in ks]
         for mode in MODES.values():
-            nfs, counts, st = run_gpu(trs, terms, 1 << 14, mode=mode)
+            nfs, counts, st = run_gpu(trs, terms, 1 << 14, **mode)
             say(f"[shared] {rhs} mode {mode}: full sweeps {st['full_sweeps']}")
             for k, nf in zip(ks, nfs):
                 np.testing.assert_array_equal(nf, CF.numeral_code(trs, 2 * k))
@@ -300,3 +305,49 @@ def test_plain_scan_kernel_agrees(case, monkeypatch):
     scan = assert_parity(trs, terms, pool, A, label=f"plain scan {case}", **opts)
     for k in ("rounds", "node_visits", "active_visits", "ready_visits", "full_sweeps", "memo_blocked"):
         assert scan[k] == base[k], k
+
+
+@pytest.mark.parametrize("case", ["fib18", "sort512", "batch_mini", "tmsort8"])
+@pytest.mark.parametrize("mode", [1, 2])
+def test_constructor_walk_and_continuation_cut_rounds(case, mode):
+    """Frontier modes' defaults against the plain notification frontier:
+    (1) the constructor walk -- a node that becomes a normal form marks the
+    constructors above it in the same round; (2) same-round continuation --
+    a workgroup examines the ready nodes it created (and roots it rewrote
+    into ready ones) in further passes of the round (by default in rounds
+    one workgroup runs alone; a fourth run takes both into wide rounds).  Normal forms and rule
+    counts equal the oracle's in all three settings; each step needs fewer
+    rounds (chains of S and cons cells cost one round instead of one per
+    cell, and a chain of plus or lt steps runs inside one round)."""
+    from paper_2009_07174_amd import predictor as PR
+    if case == "fib18":
+        trs = systems.fib()
+        terms, pool, A = [G.g_term(trs, 18)], 1 << 18, 2
+    elif case == "sort512":
+        trs = systems.msort()
+        vals = np.random.default_rng(G.BASE_SEED + 2).integers(0, 64, size=512)
+        terms, pool, A = [G.sort_term(trs, vals)], 1 << 22, 3
+    elif case == "tmsort8":
+        w = G.tmsort(8, 5)
+        trs, terms, pool, A = w.trs, w.terms, w.pool_slots, w.maxarity
+    else:
+        w = G.cfg3(96, 1 << 22, "mini")
+        trs, terms, pool, A = w.trs, w.terms, w.pool_slots, w.maxarity
+    pred = PR.init_params(len(trs.symbols), 0) if mode == 2 else None
+    off = assert_parity(trs, terms, pool, A, label=f"{case} mode {mode} no walk", mode=mode,
+                        nf_walk=-1, nf_walk_wide=-1, predictor=pred)
+    walk = assert_parity(trs, terms, pool, A, label=f"{case} mode {mode} walk", mode=mode,
+                         cont_passes=-1, predictor=pred)
+    both = assert_parity(trs, terms, pool, A, label=f"{case} mode {mode} walk + continuation",
+                         mode=mode, predictor=pred)
+    # (the same in wide rounds too: longer walks and further passes there)
+    wide = assert_parity(trs, terms, pool, A, label=f"{case} mode {mode} wide settings",
+                         mode=mode, predictor=pred, nf_walk_wide=16, cont_passes_wide=4)
+    assert wide["nf_walked"] > 0
+    say(f"[walk] {case} mode {mode}: rounds {off['rounds']} -> {walk['rounds']} -> "
+        f"{both['rounds']}, walked {walk['nf_walked']} / {both['nf_walked']}, ms "
+        f"{off['device_ms']:.1f} -> {walk['device_ms']:.1f} -> {both['device_ms']:.1f}")
+    assert off["nf_walked"] == 0
+    assert walk["nf_walked"] > 0 and both["nf_walked"] > 0
+    assert walk["rounds"] < off["rounds"]
+    assert both["rounds"] <= walk["rounds"]
