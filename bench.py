@@ -14,11 +14,11 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cfg3]
 The default workload is the batched configuration: 4096 independent terms
 (plus/times trees, g(S^n(0)) and merge sorts in equal parts) in one 2^27-slot
 pool, whose full sweeps exceed the 256 MB Infinity Cache.  The timed mode is
-the parent-notification frontier; the same workload is also run once in each
---compare mode and reported under ``compare``: the plain sweep (the paper's
-method) and the learned frontier (the predictor's parameters come from
---weights or the packaged file, else they are trained on the device first,
-outside the timed region).  The printed JSON line carries a
+the learned frontier (the predictor's parameters come from --weights or the
+packaged file, else they are trained on the device first, outside the timed
+region); the same workload is also run once in each --compare mode and
+reported under ``compare``: the plain sweep (the paper's method) and the
+parent-notification frontier without the network (the ablation).  The printed JSON line carries a
 ``roofline`` object for the round kernel (algorithmic bytes of the run /
 device time of the round loop, against 8 TB/s) and a ``cpu_baseline``
 object: the CPU oracle timed on a bounded sample of the same workload on one
@@ -298,8 +298,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cfg3")
-    ap.add_argument("--mode", default="frontier", choices=["plain", "frontier", "learned"])
-    ap.add_argument("--compare", default="plain,learned,frontier",
+    ap.add_argument("--mode", default="learned", choices=["plain", "frontier", "learned"])
+    ap.add_argument("--compare", default="plain,frontier",
                     help="comma-separated modes run once more for comparison ('' = none)")
     ap.add_argument("--weights", default=None, help="predictor parameters (.npz)")
     ap.add_argument("--threshold", type=float, default=0.1)

@@ -152,6 +152,13 @@ typedef struct {
                                 (0 = 1; -1 = off) */
   int32_t cont_passes_wide;  /* cont_passes for rounds that several
                                 workgroups run (0 or -1 = none) */
+  int32_t place_fresh;       /* placement of new nodes: 0 (default) = slots
+                                recycled by collection first, fresh slots past
+                                the extent n when none are left; k in 1..100 =
+                                fresh slots first while n is below k% of the
+                                pool, so that the nodes a round creates lie
+                                next to each other (locality), at the price of
+                                a larger extent */
 } trs_opts;
 
 typedef struct {
@@ -274,12 +281,12 @@ void trs_default_opts(trs_opts *opts);
 
 /* Autotuner of the launch shape (the batching step: block size and nodes
  * per thread; max_grid is part of the result).  Times complete trs_normalize
- * runs of the loaded terms under *base.  Frontier and learned modes: block
- * sizes 128, 256, 512, 1024 at 16 nodes per thread, then 4 and 8 nodes per
- * thread at the best block (six runs, default grid).  Plain mode, whose large
- * rounds are classified by the scan kernel and examined as lists: (block,
- * nodes per thread) in (128, 16), (128, 8), (64, 16), (256, 16) (four
- * runs).  *best
+ * runs of the loaded terms under *base, walking the block x nodes-per-thread
+ * grid in two stages: block sizes 64, 128, 256, 512, 1024 at 16 nodes per
+ * thread, then 1, 2, 4 and 8 nodes per thread at the best block (nine runs,
+ * default grid).  Plain mode, whose large rounds are classified by the scan
+ * kernel and examined as lists, leaves out block 1024 and one node per
+ * thread (seven runs).  *best
  * receives *base with the fastest block, nodes_per_thread and max_grid.  The
  * result is cached per context and loaded terms (a second call with the same
  * mode returns it without trials; res->trials = 0 then).  After the call the
@@ -290,11 +297,11 @@ typedef struct {
   int32_t best_npt;
   int32_t pad;
   double best_ms;       /* device time of the fastest trial */
-  int32_t block[8], npt[8];
-  double ms[8];         /* device time per trial */
+  int32_t block[16], npt[16];
+  double ms[16];        /* device time per trial */
   int32_t best_grid;    /* max_grid of the fastest trial (0 = default) */
   int32_t pad2;
-  int32_t grid[8];
+  int32_t grid[16];
 } trs_tune_result;
 
 trs_status trs_autotune(trs_ctx *ctx, const trs_opts *base, trs_opts *best,

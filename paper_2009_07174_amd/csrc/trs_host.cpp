@@ -493,6 +493,7 @@ void trs_default_opts(trs_opts *o) {
   o->cont_passes = 0;
   o->nf_walk_wide = 0;
   o->cont_passes_wide = 0;
+  o->place_fresh = 0;
 }
 
 trs_status trs_create(trs_ctx **out, const trs_config *cfg) {
@@ -728,6 +729,8 @@ trs_status trs_normalize(trs_ctx *c, const trs_opts *opts_in, trs_stats *stats) 
   if (o.cont_passes < -1 || o.cont_passes > (1 << 20) || o.cont_passes_wide < -1 ||
       o.cont_passes_wide > (1 << 20))
     return c->fail(TRS_E_ARG, "cont_passes and cont_passes_wide must be -1..2^20");
+  if (o.place_fresh < 0 || o.place_fresh > 100)
+    return c->fail(TRS_E_ARG, "place_fresh must be 0..100");
   if (o.label_horizon < 0 || o.sweep_every < -1)
     return c->fail(TRS_E_ARG, "label_horizon must be >= 0, sweep_every >= -1");
   if (o.trace && o.mode != TRS_MODE_PLAIN)
@@ -870,6 +873,7 @@ trs_status trs_normalize(trs_ctx *c, const trs_opts *opts_in, trs_stats *stats) 
   ra.nf_walk_wide = plain ? 0 : opt(o.nf_walk_wide, TRS_DEFAULT_WALK_WIDE);
   ra.cont_passes = ra.nf_walk ? opt(o.cont_passes, TRS_DEFAULT_CONT) : 0;
   ra.cont_passes_wide = ra.nf_walk_wide ? std::max(0, o.cont_passes_wide) : 0;
+  ra.fresh_below = (int32_t)(c->cfg.pool_slots * o.place_fresh / 100);
   // learned mode's periodic full sweeps (off by default): dropped nodes are
   // woken by parent notification, and a round that makes no progress is
   // followed by a full sweep, so these only bound how long a missed wake-up
@@ -1290,26 +1294,24 @@ trs_status trs_autotune(trs_ctx *c, const trs_opts *base, trs_opts *best, trs_tu
     if (bt.block == 0 || st.device_ms < bt.ms) bt = Tuned{B, npt, grid, st.device_ms};
     return TRS_OK;
   };
-  if (base->mode == TRS_MODE_PLAIN) {
-    // the scan kernel classifies the large full rounds, so the round
-    // kernel's shape matters for the list rounds that follow (narrow
-    // workgroups spread the examined slots over more compute units) and for
-    // small pools swept inside it
-    const int shapes[4][2] = {{128, 16}, {128, 8}, {64, 16}, {256, 16}};
-    for (const auto &sh : shapes) {
-      const trs_status s = trial(sh[0], sh[1], 0);
-      if (s != TRS_OK) return s;
-    }
-  } else {
-    for (int B : {128, 256, 512, 1024}) {
-      const trs_status s = trial(B, 16, 0);
-      if (s != TRS_OK) return s;
-    }
-    const int B0 = bt.block;
-    for (int npt : {4, 8}) {
-      const trs_status s = trial(B0, npt, 0);
-      if (s != TRS_OK) return s;
-    }
+  // Block sizes first at 16 nodes per thread, then the other nodes per
+  // thread at the best block: a staged walk over the block x nodes-per-
+  // thread grid.  In plain mode the scan kernel classifies the large full
+  // rounds, so the round kernel's shape matters for the list rounds that
+  // follow (narrow workgroups spread the examined slots over more compute
+  // units) and for small pools swept inside it; 1024-thread workgroups,
+  // which only slow the list rounds, are left out there.
+  const bool plain = base->mode == TRS_MODE_PLAIN;
+  for (int B : {64, 128, 256, 512, 1024}) {
+    if (plain && B > 512) continue;
+    const trs_status s = trial(B, 16, 0);
+    if (s != TRS_OK) return s;
+  }
+  const int B0 = bt.block;
+  for (int npt : {1, 2, 4, 8}) {
+    if (plain && npt == 1) continue;
+    const trs_status s = trial(B0, npt, 0);
+    if (s != TRS_OK) return s;
   }
   c->tuned[base->mode] = bt;
   *best = *base;

@@ -42,6 +42,8 @@ struct RoundArgs {
                         // round over the ready nodes it created or rewrote
                         // in that round, in rounds one workgroup runs
   int32_t cont_passes_wide;  // the same in rounds several workgroups run
+  int32_t fresh_below;  // allocation takes fresh slots before recycled ones
+                        // while the extent n is below this (0: never)
   int32_t use_scan;     // plain mode: large full rounds are classified by k_scan
                         // (launched before each k_round) and run as list rounds
   int32_t round_block;  // k_round's block size (for the scan's hand-over)

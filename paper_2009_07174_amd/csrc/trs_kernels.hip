@@ -416,6 +416,7 @@ __device__ __forceinline__ void retire_marker(uint8_t *state, int s, unsigned ep
 
 struct RoundCtx {
   int r, n, fsP, mode;
+  int room;   // claims below this take fresh slots first (locality placement)
   bool walk;     // constructor walk (nf_walk) on in this round
   int walk_max;  // constructors one walk may mark in this round
   int cbuf;      // >= 0: ready nodes this thread creates or rewrites go to
@@ -856,8 +857,12 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
   for (int j = 0; j < MAXNEW; j++) {
     if (j < m) {
       const int c = base.x + j;
-      const int64_t slot =
-          (c < R.fsP) ? (int64_t)R.SP[R.fsP - 1 - c] : (int64_t)R.n + (c - R.fsP);
+      // claim c: fresh slots n, n+1, ... for the first R.room claims, then
+      // the recycled slots on the free stack, then fresh slots again
+      const int cr = c - R.room;
+      const int64_t slot = c < R.room ? (int64_t)R.n + c
+                           : cr < R.fsP ? (int64_t)R.SP[R.fsP - 1 - cr]
+                                        : (int64_t)R.n + (c - R.fsP);
       if (slot >= N || slot <= 0) okalloc = false;
       ns[j] = (int)slot;
     }
@@ -1125,6 +1130,14 @@ __device__ __forceinline__ int collect(const RoundArgs &a, const Lds &L, RoundCn
   return d;
 }
 
+// Locality placement (option): while the extent n is below fresh_below,
+// a round's first claims take fresh slots past n, which lie next to each
+// other and to the nodes created just before, instead of recycled slots
+// scattered over the pool.  Returns how many claims go fresh first.
+__device__ __forceinline__ int fresh_room(const RoundArgs &a, int n) {
+  return a.fresh_below > n ? a.fresh_below - n : 0;
+}
+
 // State of round r, derived from the counters of round r-1.
 // published flags (pub[9], besides err << 8)
 #define PUB_STOP 1
@@ -1175,7 +1188,7 @@ __device__ __forceinline__ RoundState round_state(const RoundArgs &a, int r) {
     const int pn = ld(&ctl->n[p3]), pf0 = ld(&ctl->fs[p3][0]), pf1 = ld(&ctl->fs[p3][1]);
     const int P = (r - 1) & 1;  // stack popped in round r-1
     const int fsP = P ? pf1 : pf0;
-    const int used = min(c_alloc, fsP);
+    const int used = min(max(c_alloc - fresh_room(a, pn), 0), fsP);
     const int64_t nn = (int64_t)pn + (c_alloc - used);
     n = (int)min(nn, (int64_t)p.N);
     if (P == 0) {
@@ -1424,6 +1437,7 @@ __device__ __forceinline__ void round_execute(const RoundArgs &a, Lds &L, const 
   R.stamp = rs.stamp + r;
   R.SP = (r & 1) ? p.fstack1 : p.fstack0;
   R.fsP = (r & 1) ? fs1 : fs0;
+  R.room = fresh_room(a, n);
   int32_t *SQ = ((r + 1) & 1) ? p.fstack1 : p.fstack0;
   const int fsQ = ((r + 1) & 1) ? fs1 : fs0;
   L.qd.out = (r & 1) ? p.dead1 : p.dead0;

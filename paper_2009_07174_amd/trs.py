@@ -42,7 +42,7 @@ class trs_opts(ctypes.Structure):
                 ("sweep_every", ctypes.c_int32), ("max_grid", ctypes.c_int32),
                 ("pf_depth", ctypes.c_int32), ("nf_walk", ctypes.c_int32),
                 ("cont_passes", ctypes.c_int32), ("nf_walk_wide", ctypes.c_int32),
-                ("cont_passes_wide", ctypes.c_int32)]
+                ("cont_passes_wide", ctypes.c_int32), ("place_fresh", ctypes.c_int32)]
 
 
 class trs_stats(ctypes.Structure):
@@ -88,10 +88,10 @@ class trs_train_result(ctypes.Structure):
 class trs_tune_result(ctypes.Structure):
     _fields_ = [("trials", ctypes.c_int32), ("best_block", ctypes.c_int32),
                 ("best_npt", ctypes.c_int32), ("pad", ctypes.c_int32),
-                ("best_ms", ctypes.c_double), ("block", ctypes.c_int32 * 8),
-                ("npt", ctypes.c_int32 * 8), ("ms", ctypes.c_double * 8),
+                ("best_ms", ctypes.c_double), ("block", ctypes.c_int32 * 16),
+                ("npt", ctypes.c_int32 * 16), ("ms", ctypes.c_double * 16),
                 ("best_grid", ctypes.c_int32), ("pad2", ctypes.c_int32),
-                ("grid", ctypes.c_int32 * 8)]
+                ("grid", ctypes.c_int32 * 16)]
 
     def as_dict(self):
         k = self.trials
@@ -423,13 +423,14 @@ class Options:
     cont_passes: int = 0
     nf_walk_wide: int = 0
     cont_passes_wide: int = 0
+    place_fresh: int = 0
 
     def to_c(self) -> trs_opts:
         o = trs_default_opts()
         for k in ("mode", "block", "nodes_per_thread", "rounds_per_poll", "max_rounds",
                   "threshold", "persistent", "trace", "trace_cap", "label_horizon",
                   "sweep_every", "max_grid", "pf_depth", "nf_walk", "cont_passes",
-                  "nf_walk_wide", "cont_passes_wide"):
+                  "nf_walk_wide", "cont_passes_wide", "place_fresh"):
             setattr(o, k, getattr(self, k))
         return o
 

@@ -28,6 +28,8 @@ MODES = {"plain": dict(mode=0), "frontier": dict(mode=1),
          "frontier_nowalk": dict(mode=1, nf_walk=-1, nf_walk_wide=-1),
          "frontier_nocont": dict(mode=1, cont_passes=-1),
          "frontier_wide": dict(mode=1, nf_walk_wide=8, cont_passes_wide=4),
+         "frontier_fresh": dict(mode=1, place_fresh=50),
+         "plain_fresh": dict(mode=0, place_fresh=50),
          "learned": dict(mode=2)}
 
 

@@ -130,10 +130,12 @@ def test_fast_growing_term_resizes_the_grid(mode):
 
 
 @pytest.mark.parametrize("mode", MODES)
-def test_tree_merge_sort(mode):
+@pytest.mark.parametrize("depth", [8, 12])
+def test_tree_merge_sort(mode, depth):
     """The paper's tree merge sort (5-argument Merge2, maxarity 5): a tree of
-    depth 8 over 256 lists of 5 values, the generator the benchmark uses."""
-    w = G.tmsort(8, 5)
+    depth 8 (12) over 256 (4096) lists of 5 values, the generator the
+    benchmark uses at depth 23."""
+    w = G.tmsort(depth, 5)
     assert_parity(w.trs, w.terms, w.pool_slots, w.maxarity, label=f"{w.name} {mode}",
                   **MODES[mode])
 
@@ -244,9 +246,11 @@ def test_autotune_plain_tunes_the_grid():
         ctx.load_term_list(w.terms)
         best, res = ctx.autotune(T.Options(mode=0))
         say(f"[autotune plain] {res}")
-        assert res["trials"] == 4
-        assert [(b, npt) for b, npt, _, _ in res["table"]] == [(128, 16), (128, 8), (64, 16),
-                                                                (256, 16)]
+        assert res["trials"] == 7
+        tab = [(b, npt) for b, npt, _, _ in res["table"]]
+        assert tab[:4] == [(64, 16), (128, 16), (256, 16), (512, 16)]
+        b0 = min(res["table"][:4], key=lambda t: t[3])[0]
+        assert tab[4:] == [(b0, 2), (b0, 4), (b0, 8)]
         assert (best.block, best.nodes_per_thread) == (res["best_block"], res["best_npt"])
         ctx.normalize(best)
         nfs = [ctx.read_nf(i) for i in range(len(w.terms))]
@@ -265,7 +269,7 @@ def test_autotune_picks_a_shape_and_keeps_results():
         ctx.load_term_list(w.terms)
         best, res = ctx.autotune(T.Options(mode=1))
         say(f"[autotune] {res}")
-        assert res["trials"] == 6
+        assert res["trials"] == 9
         assert (best.block, best.nodes_per_thread) == (res["best_block"], res["best_npt"])
         assert res["best_ms"] == min(ms for _, _, _, ms in res["table"])
         best2, res2 = ctx.autotune(T.Options(mode=1))   # cached
@@ -351,3 +355,28 @@ def test_constructor_walk_and_continuation_cut_rounds(case, mode):
     assert walk["nf_walked"] > 0 and both["nf_walked"] > 0
     assert walk["rounds"] < off["rounds"]
     assert both["rounds"] <= walk["rounds"]
+
+
+@pytest.mark.parametrize("case", ["g16", "batch_mini", "ttree12"])
+@pytest.mark.parametrize("mode", [0, 1])
+def test_fresh_placement(case, mode):
+    """Locality placement (place_fresh): new nodes take fresh slots past the
+    extent before recycled ones while the extent is below half the pool.
+    Results equal the oracle's; the extent grows beyond the recycling run's
+    (slots are not reused while there is room) but stays within the pool."""
+    if case == "g16":
+        trs = systems.fib()
+        terms, pool, A = [G.g_term(trs, 16)], 1 << 20, 2
+    elif case == "ttree12":
+        w = G.ttree(12, pool_slots=1 << 20)
+        trs, terms, pool, A = w.trs, w.terms, w.pool_slots, w.maxarity
+    else:
+        w = G.cfg3(96, 1 << 22, "mini")
+        trs, terms, pool, A = w.trs, w.terms, w.pool_slots, w.maxarity
+    base = assert_parity(trs, terms, pool, A, label=f"{case} mode {mode} recycled first", mode=mode)
+    fresh = assert_parity(trs, terms, pool, A, label=f"{case} mode {mode} fresh first", mode=mode,
+                          place_fresh=50)
+    say(f"[placement] {case} mode {mode}: peak {base['peak_slots']} -> {fresh['peak_slots']}, "
+        f"ms {base['device_ms']:.1f} -> {fresh['device_ms']:.1f}")
+    assert fresh["peak_slots"] >= base["peak_slots"]
+    assert fresh["peak_slots"] <= pool
