@@ -310,6 +310,8 @@ def main():
     ap.add_argument("--npt", type=int, default=0)
     ap.add_argument("--max-grid", type=int, default=0, help="workgroups per launch cap (0 = default)")
     ap.add_argument("--pf-depth", type=int, default=0, help="sweep tiles prefetched (0 = as fit)")
+    ap.add_argument("--place-fresh", type=int, default=0,
+                    help="fresh slots first while the extent is below this %% of the pool")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default (or given) block and nodes per thread")
@@ -339,7 +341,7 @@ def main():
         ctx.set_predictor(load_predictor(w, args.weights))
     opts = T.Options(block=args.block, nodes_per_thread=args.npt, mode=MODES[args.mode],
                      persistent=1 if args.persistent else 0, threshold=args.threshold, sweep_every=args.sweep_every,
-                     max_grid=args.max_grid, pf_depth=args.pf_depth)
+                     max_grid=args.max_grid, pf_depth=args.pf_depth, place_fresh=args.place_fresh)
     tune = None
     if not args.no_autotune and not args.block and not args.npt:
         # the launch shape is tuned on complete runs (seconds each): on the

@@ -182,6 +182,9 @@ typedef struct {
   int64_t trace_records; /* trace records logged (may exceed trace_cap) */
   int64_t nf_walked;     /* constructors marked normal forms by the walk of
                             trs_opts.nf_walk (not counted in nf_set) */
+  int64_t last_progress_round; /* last round in which a node fired or became a
+                            normal form; the rounds after it only collected
+                            garbage and confirmed the normal forms */
   double device_ms;      /* device time of the round loop (HIP events) */
 } trs_stats;
 

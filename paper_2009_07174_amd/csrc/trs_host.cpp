@@ -1211,6 +1211,7 @@ trs_status trs_normalize(trs_ctx *c, const trs_opts *opts_in, trs_stats *stats) 
     stats->mlp_kept = sum(STAT_KEEP);
     stats->trace_records = sum(STAT_TRACE);
     stats->nf_walked = sum(STAT_WALK);
+    stats->last_progress_round = h.last_prog;
     stats->device_ms = ms;
   }
   if (result != TRS_OK) return result;

@@ -1833,7 +1833,10 @@ __device__ __forceinline__ void round_execute(const RoundArgs &a, Lds &L, const 
   // serialise)
   if (tid == 0 && (Ga == 1 || a.nrounds > 0)) {
     if (L.misc[32]) st(&cnt->active, 1);
-    if (L.misc[33]) st(&cnt->prog, 1);
+    if (L.misc[33]) {
+      st(&cnt->prog, 1);
+      st(&ctl->last_prog, r);
+    }
     L.misc[32] = L.misc[33] = 0;
   }
   if (tid == 0) L.misc[24] = L.misc[25] = L.misc[26] = 0;  // the sweep's tile counters
@@ -1991,7 +1994,10 @@ __global__ void __launch_bounds__(MAXB) k_round(RoundArgs a) {
       if (flags) {
         RoundCnt *c0 = &ctl->cnt[r0 % 3];
         if (flags & 1) st(&c0->active, 1);
-        if (flags & 2) st(&c0->prog, 1);
+        if (flags & 2) {
+          st(&c0->prog, 1);
+          st(&ctl->last_prog, r0);
+        }
       }
       if (scanned0) {
         // every workgroup read the scan's counts at launch start: clear them

@@ -143,7 +143,8 @@ struct Ctl {
   int32_t full_sweeps; // rounds that swept every slot
   int32_t r_reached;   // round after the last one workgroup 0 ran alone
   int32_t fs_final[2]; // free-stack sizes when the run ended
-  int32_t pad2[2];
+  int32_t last_prog;   // last round in which a node fired or became a normal form
+  int32_t pad2;
   alignas(128) RoundCnt cnt[3];  // counters accumulated during round r (index r % 3)
   // state of the next launch's first round, published by the last workgroup
   // of a launch (the host writes it for round 0): done, r, need, n, fs0, fs1,

@@ -49,7 +49,8 @@ class trs_stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in (
         "rounds", "rule_apps", "node_visits", "active_visits", "allocs", "frees",
         "peak_slots", "gc_rounds", "mlp_evals", "full_sweeps", "launches", "ready_visits",
-        "nf_set", "rc_atomics", "memo_blocked", "mlp_kept", "trace_records", "nf_walked")] + [
+        "nf_set", "rc_atomics", "memo_blocked", "mlp_kept", "trace_records", "nf_walked",
+        "last_progress_round")] + [
         ("device_ms", ctypes.c_double)]
 
     def as_dict(self):

@@ -143,6 +143,13 @@ def test_call_order_and_term_errors():
     with pytest.raises(T.TRSError) as e:
         c.normalize(T.Options(nodes_per_thread=3))
     assert e.value.code == T.TRS_E_ARG
+    # the frontier modes' walk and continuation bounds and the placement
+    # share are range-checked before any device work
+    for bad in (dict(nf_walk=-2), dict(nf_walk_wide=-5), dict(cont_passes=-2),
+                dict(cont_passes_wide=1 << 21), dict(place_fresh=101), dict(place_fresh=-1)):
+        with pytest.raises(T.TRSError) as e:
+            c.normalize(T.Options(mode=T.TRS_MODE_FRONTIER, **bad))
+        assert e.value.code == T.TRS_E_ARG, bad
     c.close()
 
 
