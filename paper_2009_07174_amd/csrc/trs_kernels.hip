@@ -627,6 +627,33 @@ __device__ __forceinline__ int even_bits(unsigned x) {
   return (int)x;
 }
 
+// A dead-list entry whose node already dropped its references to its
+// arguments (in the round it died); slot indices stay below 2^30.
+#define DEAD_RELEASED 0x40000000
+
+// Drop one reference to each argument of dead node d; arguments whose
+// count reaches zero go on the dead list (their own arguments still held).
+template <int A>
+__device__ __forceinline__ void release_args(const RoundArgs &a, const Lds &L, RoundCnt *cnt,
+                                             int d, Counters &C) {
+  const Pool &p = a.p;
+  const int f = p.hss[d];
+  const int ar = ((unsigned)f < (unsigned)a.n_sym) ? SYM_ARITY(L.tab[TAB_SYM + f]) : 0;
+#pragma unroll
+  for (int j = 0; j < A; j++) {
+    if (j < ar) {
+      const int c = p.args[(int64_t)d * A + j];
+      if ((unsigned)c >= (unsigned)p.N || c == 0) {
+        st(&cnt->err, -9);
+        continue;
+      }
+      const int old = atomicSub(&p.rc[c], 1);
+      C.rcops++;
+      if (old == 1) qpush(L, L.qd, c, p.N);
+    }
+  }
+}
+
 // Examine slot s (s <= 0: idle lane) and rewrite it if it is a redex whose
 // arguments are all normal forms.  memo: the slot's memo bits.  Must be
 // called by every thread of the workgroup (contains the allocation barrier);
@@ -1065,15 +1092,30 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
         dold[i] = atomicAdd(&p.rc[dslot[i]], d) + d;
       }
     }
+    // A node whose count reaches zero goes on the dead list; its slot is
+    // freed next round.  In rounds with further passes it drops its own
+    // references at once: a chain consumed one cell per pass (the peeling
+    // of a numeral) would otherwise die one cell per round after the
+    // passes, each cell held by the dead one above it until that is
+    // collected.  (Its slot still waits for the next round, when no list
+    // of this round can name it any more.)
+    auto dead = [&](int x) {
+      if (R.cbuf >= 0) {
+        release_args<A>(a, L, cnt, x, C);
+        qpush(L, L.qd, x | DEAD_RELEASED, N);
+      } else {
+        qpush(L, L.qd, x, N);
+      }
+    };
 #pragma unroll
     for (int i = 0; i < NEG_BATCH; i++)
-      if (i < nneg && dold[i] == 0) qpush(L, L.qd, dslot[i], N);
+      if (i < nneg && dold[i] == 0) dead(dslot[i]);
     for (int i = NEG_BATCH; i < nneg; i++) {
       const int dw = tab[dl + npos + i];
       const int d = (int)(int8_t)((dw >> 8) & 0xff);
       const int slot = pslot(dw & 0xff);
       const int old = atomicAdd(&p.rc[slot], d);
-      if (old + d == 0) qpush(L, L.qd, slot, N);
+      if (old + d == 0) dead(slot);
     }
     C.rcops += npos + nneg;
   } else if (nfset) {
@@ -1100,31 +1142,19 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
   tmark(a, L, R.r, 10);
 }
 
-// Collect dead node d: drop one reference to each argument, mark the slot
-// free.  Returns d if it is to be pushed on the free stack, else 0.
+// Collect dead-list entry e: drop one reference to each argument of its
+// node (unless it did so when it died), mark the slot free.  Returns the
+// slot, to be pushed on the free stack, or 0.
 template <int A>
-__device__ __forceinline__ int collect(const RoundArgs &a, const Lds &L, RoundCnt *cnt, int d,
+__device__ __forceinline__ int collect(const RoundArgs &a, const Lds &L, RoundCnt *cnt, int e,
                                        Counters &C) {
   const Pool &p = a.p;
+  const int d = e & ~DEAD_RELEASED;
   if ((unsigned)d >= (unsigned)p.N || d == 0) {
     st(&cnt->err, -9);
     return 0;
   }
-  const int f = p.hss[d];
-  const int ar = ((unsigned)f < (unsigned)a.n_sym) ? SYM_ARITY(L.tab[TAB_SYM + f]) : 0;
-#pragma unroll
-  for (int j = 0; j < A; j++) {
-    if (j < ar) {
-      const int c = p.args[(int64_t)d * A + j];
-      if ((unsigned)c >= (unsigned)p.N || c == 0) {
-        st(&cnt->err, -9);
-        continue;
-      }
-      const int old = atomicSub(&p.rc[c], 1);
-      C.rcops++;
-      if (old == 1) qpush(L, L.qd, c, p.N);
-    }
-  }
+  if (!(e & DEAD_RELEASED)) release_args<A>(a, L, cnt, d, C);
   p.state[d] = (uint8_t)ST_FREE;
   C.freed++;
   return d;
