@@ -123,12 +123,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(workload: str, mode: str, block: int, npt: int):
-    """HBM bytes per launch of the round kernel from the committed counter
-    summary (profiles/*.md, a fenced json block): FETCH_SIZE and WRITE_SIZE
-    per launch, each scaled by what the counter reads for a copy of known
-    size.  None unless the summary was taken on this workload, mode and
-    launch shape with the current kernel source."""
+def measured_profile(workload: str, mode: str, block: int, npt: int):
+    """The committed counter summary (profiles/*.md, a fenced json block) of
+    the round kernel on this workload, mode and launch shape, or None unless
+    it was taken with the current kernel source."""
     import glob
     import re
     for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
@@ -141,12 +139,36 @@ def measured_traffic(workload: str, mode: str, block: int, npt: int):
             continue
         if (d.get("workload"), d.get("mode"), d.get("block"), d.get("npt")) != (workload, mode, block, npt):
             continue
-        if d.get("source_sha256") != kernel_source_hash():
-            return None
-        if d.get("fetch_bytes_per_launch") is None or d.get("write_bytes_per_launch") is None:
-            return None
-        return d["fetch_bytes_per_launch"] + d["write_bytes_per_launch"]
+        return d if d.get("source_sha256") == kernel_source_hash() else None
     return None
+
+
+def atomics_roofline(workload: str, mode: str, block: int, npt: int, avg_launch_us: float):
+    """Atomic throughput of the round kernel: the atomics per launch that
+    the L2 counted (rocprofv3 TCC_ATOMIC, calibrated against a kernel of
+    known atomic count) over this run's average launch time, against the
+    random-atomic rate trs_membench measured on the same GPU."""
+    d = measured_profile(workload, mode, block, npt)
+    if not d or d.get("atomics_per_launch") is None or not avg_launch_us:
+        return None
+    ach = d["atomics_per_launch"] / (avg_launch_us * 1e-6)
+    peak = d.get("membench_atomic_peak_per_s")
+    return {"achieved": ach, "peak": peak, "unit": "atomics/s",
+            "frac": ach / peak if peak else None,
+            "per_launch": d["atomics_per_launch"],
+            "source": "rocprofv3 --pmc TCC_ATOMIC (profiles/), trs_membench random atomics"}
+
+
+def measured_traffic(workload: str, mode: str, block: int, npt: int):
+    """HBM bytes per launch of the round kernel from the committed counter
+    summary: FETCH_SIZE and WRITE_SIZE per launch, each scaled by what the
+    counter reads for a copy of known size.  None unless the summary was
+    taken on this workload, mode and launch shape with the current kernel
+    source."""
+    d = measured_profile(workload, mode, block, npt)
+    if not d or d.get("fetch_bytes_per_launch") is None or d.get("write_bytes_per_launch") is None:
+        return None
+    return d["fetch_bytes_per_launch"] + d["write_bytes_per_launch"]
 
 
 def cpu_baseline(w, budget_s: float = 15.0):
@@ -424,7 +446,10 @@ def main():
                                      "copy-calibrated)",
                      "kernel": "k_round", "launches_per_step": st["launches"],
                      "bytes_per_launch": ab["total"] / max(st["launches"], 1),
-                     "avg_launch_us": 1e3 * ev_ms_step / max(st["launches"], 1)},
+                     "avg_launch_us": 1e3 * ev_ms_step / max(st["launches"], 1),
+                     "atomics": atomics_roofline(w.name, args.mode, opts.block,
+                                                 opts.nodes_per_thread,
+                                                 1e3 * ev_ms_step / max(st["launches"], 1))},
         "stats": st,
     }
     if compare:

@@ -205,6 +205,7 @@ struct Queue {
   int32_t *gcount;  // global length
   int cap_lds;
   int slot;         // index of the LDS counter in misc[]
+  int lc;           // index in misc[] of the list's length in a solo round
 };
 
 struct Lds {
@@ -234,7 +235,13 @@ struct Lds {
   // round (counts in misc[7] and misc[27]); cap entries each
   int32_t *cb0, *cb1;
   int ccap;
+  // the workgroup runs the round alone: the round's claim and list
+  // counters are kept in LDS at misc[LC_SLOT ..] (alloc, push, dead,
+  // frontier, retire; Queue::lc indexes the list ones) and stored to the
+  // control block at the end of the round
+  bool solo;
 };
+#define LC_SLOT 35
 
 #define LSTAT_GC CTL_NSTAT
 #define LSTAT_FULL (CTL_NSTAT + 1)
@@ -246,7 +253,15 @@ __device__ __forceinline__ void qpush(const Lds &L, const Queue &q, int32_t v, i
   if (i < q.cap_lds) {
     q.buf[i] = v;
   } else {  // LDS buffer full: append directly
-    int g = atomicAdd(q.gcount, 1);
+    // (the LDS count through an LDS-typed pointer: a generic one selected
+    // against the global counter is not compiled correctly)
+    int g;
+    if (L.solo) {
+      auto *lcnt = (__attribute__((address_space(3))) int32_t *)(L.misc + q.lc);
+      g = __hip_atomic_fetch_add(lcnt, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    } else {
+      g = atomicAdd(q.gcount, 1);
+    }
     if (g < cap) q.out[g] = v;
   }
 }
@@ -264,7 +279,16 @@ __device__ __forceinline__ void qpush_cont(const Lds &L, int k, int32_t v, int64
 
 __device__ __forceinline__ void qreserve(const Lds &L, const Queue &q, int k) {
   const int nb = min(L.misc[q.slot], q.cap_lds);
-  L.misc[4 + k] = nb > 0 ? atomicAdd(q.gcount, nb) : 0;
+  int b = 0;
+  if (nb > 0) {
+    if (L.solo) {
+      b = L.misc[q.lc];
+      L.misc[q.lc] = b + nb;
+    } else {
+      b = atomicAdd(q.gcount, nb);
+    }
+  }
+  L.misc[4 + k] = b;
 }
 
 // Flush one LDS queue's buffered entries (whole workgroup; k = flush slot).
@@ -315,8 +339,15 @@ __device__ __forceinline__ int2 wg_reserve2(const Lds &L, int m1, int32_t *c1, i
       r1 += t1;
       r2 += t2;
     }
-    L.misc[4] = r1 ? atomicAdd(c1, r1) : 0;
-    L.misc[5] = r2 ? atomicAdd(c2, r2) : 0;
+    if (L.solo) {  // (alone in the round: the counts are in LDS)
+      L.misc[4] = L.misc[LC_SLOT];
+      L.misc[5] = L.misc[LC_SLOT + 1];
+      L.misc[LC_SLOT] += r1;
+      L.misc[LC_SLOT + 1] += r2;
+    } else {
+      L.misc[4] = r1 ? atomicAdd(c1, r1) : 0;
+      L.misc[5] = r2 ? atomicAdd(c2, r2) : 0;
+    }
   }
   lds_sync();
   int2 b;
@@ -1470,6 +1501,17 @@ __device__ __forceinline__ void round_execute(const RoundArgs &a, Lds &L, const 
   R.room = fresh_room(a, n);
   int32_t *SQ = ((r + 1) & 1) ? p.fstack1 : p.fstack0;
   const int fsQ = ((r + 1) & 1) ? fs1 : fs0;
+  // A workgroup that runs the round alone is the only one to claim slots
+  // and append to the round's lists, so it counts them in LDS (an LDS
+  // atomic instead of a global one on each pass's dependent chain) and
+  // stores the totals once, at the end of the round.
+  const bool solo = Ga == 1;
+  int32_t *lc = L.misc + LC_SLOT;  // alloc, push, dead, front, retire
+  if (solo) {
+    if (tid < 5) lc[tid] = 0;
+    lds_sync();
+  }
+  L.solo = solo;
   L.qd.out = (r & 1) ? p.dead1 : p.dead0;
   L.qd.gcount = &cnt->dead;
   L.qf.out = (r & 1) ? p.front1 : p.front0;
@@ -1562,7 +1604,14 @@ __device__ __forceinline__ void round_execute(const RoundArgs &a, Lds &L, const 
       if (nc == 0) break;
       if (pass >= R.cont) {
         // the rest: one reservation on the frontier, then the copy
-        if (tid == 0) L.misc[4] = atomicAdd(L.qf.gcount, nc);
+        if (tid == 0) {
+          if (L.solo) {
+            L.misc[4] = L.misc[L.qf.lc];
+            L.misc[L.qf.lc] += nc;
+          } else {
+            L.misc[4] = atomicAdd(L.qf.gcount, nc);
+          }
+        }
         __syncthreads();
         const int gb = L.misc[4];
         for (int i = tid; i < nc; i += B)
@@ -1870,6 +1919,14 @@ __device__ __forceinline__ void round_execute(const RoundArgs &a, Lds &L, const 
     L.misc[32] = L.misc[33] = 0;
   }
   if (tid == 0) L.misc[24] = L.misc[25] = L.misc[26] = 0;  // the sweep's tile counters
+  if (solo && tid == 0) {
+    // (the round's counts, for the derivation of the next round)
+    st(&cnt->alloc, lc[0]);
+    st(&cnt->push, lc[1]);
+    st(&cnt->dead, lc[2]);
+    st(&cnt->front, lc[3]);
+    st(&cnt->ret, lc[4]);
+  }
   // end of the round: every wave's global writes complete before the
   // workgroup goes on (workgroup 0 may run the next round itself)
   __syncthreads();
@@ -1920,6 +1977,10 @@ __device__ __forceinline__ Lds setup_lds(const RoundArgs &a, int32_t *smem, bool
   L.qd.slot = 1;
   L.qf.slot = 2;
   L.qr.slot = 3;
+  L.qd.lc = LC_SLOT + 2;
+  L.qf.lc = LC_SLOT + 3;
+  L.qr.lc = LC_SLOT + 4;
+  L.solo = false;
   L.cb0 = q + 3 * qc;
   L.cb1 = q + 4 * qc;
   L.ccap = qc;
