@@ -943,6 +943,16 @@ trs_status trs_normalize(trs_ctx *c, const trs_opts *opts_in, trs_stats *stats) 
   const int TILE = B * npt;
   HIPCHK(c, trs_prepare_kernels(A, lds));
   int gmax = o.max_grid > 0 ? o.max_grid : 8 * c->cu_count;
+  if (!o.persistent) {
+    // The grid of a round launch stays within what the chip holds at once,
+    // so that every workgroup is dispatched, and reads the published line,
+    // at the launch's start.  A workgroup dispatched only after the working
+    // ones had finished (one that had to wait for a free slot) would read
+    // the line the last of them published for the next launch, and could
+    // run that round a second time.
+    const int res = trs_round_resident(A, B, lds, c->cfg.device);
+    if (res > 0) gmax = std::min(gmax, res);
+  }
   if (o.persistent) {
     gmax = trs_max_resident(A, B, lds, c->cfg.device);
     if (gmax <= 0) return c->fail(TRS_E_HIP, "persistent kernel cannot be resident");

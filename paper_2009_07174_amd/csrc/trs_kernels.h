@@ -108,3 +108,6 @@ hipError_t trs_launch_persistent(int A, const RoundArgs &a, int grid, int block,
 
 // Highest number of co-resident workgroups for the persistent kernel.
 int trs_max_resident(int A, int block, size_t lds_bytes, int device);
+
+// Highest number of co-resident workgroups of the round kernel.
+int trs_round_resident(int A, int block, size_t lds_bytes, int device);

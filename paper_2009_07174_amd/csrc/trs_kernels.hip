@@ -2419,6 +2419,26 @@ hipError_t trs_launch_persistent(int A, const RoundArgs &a, int grid, int block,
   return hipGetLastError();
 }
 
+template <int A>
+static void occ_round_A(int *out, int block, size_t lds) {
+  if (block <= 256)
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(out, k_round<A, 256>, block, lds);
+  else
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(out, k_round<A, 1024>, block, lds);
+}
+
+int trs_round_resident(int A, int block, size_t lds_bytes, int device) {
+  int per_cu = 0;
+  auto run = [&]() -> hipError_t {
+    DISPATCH_A(A, occ_round_A, &per_cu, block, lds_bytes);
+    return hipSuccess;
+  };
+  if (run() != hipSuccess) return 0;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return 0;
+  return per_cu * prop.multiProcessorCount;
+}
+
 int trs_max_resident(int A, int block, size_t lds_bytes, int device) {
   int per_cu = 0;
   auto run = [&]() -> hipError_t {

@@ -103,6 +103,17 @@ def test_launch_shapes_agree(block, npt, mode):
                   **MODES[mode])
 
 
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_grid_cap_beyond_residency(mode):
+    """A grid cap far above what the chip holds at once, on a batch whose
+    sweep spans thousands of tiles of 64 slots: the round launches are kept
+    within the resident set, so every workgroup reads the published round
+    before any working one ends, and the normal forms agree."""
+    w = G.cfg3(n_terms=1024, pool_slots=1 << 22, scale="mini")
+    assert_parity(w.trs, w.terms, w.pool_slots, w.maxarity, label=f"grid cap mode {mode}",
+                  mode=mode, block=64, nodes_per_thread=1, max_grid=1 << 16)
+
 @pytest.mark.parametrize("mode", MODES)
 def test_ttree(mode):
     w = G.ttree(10, pool_slots=1 << 18)
