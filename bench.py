@@ -496,7 +496,13 @@ def main():
                     "traffic_unit": "bytes per round launch (k_scan + k_round, copy-calibrated)",
                     "kernel": "k_scan + k_round", "mode": "plain", "rounds": sm["rounds"],
                     "round_launches_per_step": sm["launches"],
-                    "bytes_per_round": abm / R, "us_per_round": 1e6 * dev_s / R}
+                    "bytes_per_round": abm / R, "us_per_round": 1e6 * dev_s / R,
+                    "basis": "algorithmic bytes: an estimate of what the method must move "
+                             "(per visited slot, active visit and rule application), "
+                             "not measured traffic"}
+                rf = res["roofline_full_sweep"]
+                if rf["traffic"]:
+                    rf["measured_frac"] = rf["traffic"] / (rf["us_per_round"] * 1e-6) / 1e9 / HBM_PEAK_GBPS
     if compare:
         # speedups over the plain sweep (the paper's method), from the time
         # of one normalisation in each mode
