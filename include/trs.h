@@ -116,7 +116,7 @@ typedef struct {
   int64_t trace_cap;         /* records kept (0 = 1<<24); later ones dropped */
   int32_t label_horizon;     /* tracing: a record is labelled 1 when its node
                                 fires or becomes a normal form within this
-                                many rounds (1 = the next round; 0 = 8) */
+                                many rounds (0 = 1: the next round) */
   int32_t sweep_every;       /* learned mode: also sweep every slot every k
                                 rounds (0 or -1 = never: only when the
                                 frontier is empty or a round stalls); a node

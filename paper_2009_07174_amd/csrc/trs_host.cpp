@@ -881,7 +881,7 @@ trs_status trs_normalize(trs_ctx *c, const trs_opts *opts_in, trs_stats *stats) 
   // rounds, 3.4 s every 64)
   ra.sweep_every = o.mode == TRS_MODE_LEARNED ? std::max(0, o.sweep_every) : 0;
   if (o.trace) {
-    ra.label_h = o.label_horizon > 0 ? o.label_horizon : 8;
+    ra.label_h = o.label_horizon > 0 ? o.label_horizon : 1;
     ra.trace_rate = (uint32_t)o.trace;
     ra.trace_cap_rec = tcap;
     ra.trace_rec = c->d_trace_rec;

@@ -696,6 +696,7 @@ template <int A>
 struct Pre {
   bool have;
   int f, par;
+  int lc;  // round of the slot's last change (learned mode and tracing)
   VecA<A> raw;
 };
 
@@ -719,6 +720,7 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
   // states, so that matching such patterns needs no further read)
   GcVec<A> gc = (GcVec<A>)(0);
   int par_s = 0;  // parent hint (frontier mode), read with the slot's entries
+  int lc_s = 0;   // round of the slot's last change (track), read with them too
   bool ready = false;
   int nfb = -1;  // >= 0: the slot was examined and is blocked; bit j set when
                  // argument j is a visible normal form or j >= arity
@@ -732,11 +734,13 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
       f = pre.f;
       raw = pre.raw;
       par_s = pre.par;
+      lc_s = pre.lc;
     } else {
       f = p.hss[s];
 #pragma unroll
       for (int j = 0; j < A; j++) raw[j] = p.args[(int64_t)s * A + j];
       if (R.mode != 0) par_s = p.par[s];
+      if (track) lc_s = p.lastchg[s];
     }
     {
       if ((unsigned)f >= (unsigned)a.n_sym) {
@@ -790,7 +794,7 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
   if (nfb >= 0 && (R.mode == 2 || a.trace_rate)) {
     // a blocked node after a full readiness test: learned mode asks the
     // predictor whether to examine it again next round; tracing samples it
-    const int bk = age_bucket(R.r - p.lastchg[s]);
+    const int bk = age_bucket(R.r - lc_s);
     if (R.mode == 2) {
       // kept: examined next round (no memo, so a full sweep tests it in
       // full too); dropped: sleeps on its first blocking argument until a
@@ -1566,6 +1570,7 @@ __device__ __forceinline__ void round_execute(const RoundArgs &a, Lds &L, const 
 #pragma unroll
           for (int j = 0; j < A; j++) pre.raw[j] = p.args[(int64_t)x * A + j];
           pre.par = R.mode != 0 ? p.par[x] : 0;
+          pre.lc = (R.mode == 2 || a.trace_rate) ? p.lastchg[x] : 0;
           if ((st & ST_PEND) && ((st >> 2) & 1u) != R.e) {  // retire its own marker
             st = (st & ST_NF) ? ST_NF : ST_ACTIVE;
             p.state[x] = (uint8_t)st;
@@ -1636,6 +1641,7 @@ __device__ __forceinline__ void round_execute(const RoundArgs &a, Lds &L, const 
 #pragma unroll
             for (int j = 0; j < A; j++) pre.raw[j] = p.args[(int64_t)v * A + j];
             pre.par = p.par[v];
+            pre.lc = (R.mode == 2 || a.trace_rate) ? p.lastchg[v] : 0;
             if ((st & (ST_ACTIVE | ST_PEND | ST_NF)) == ST_ACTIVE) x = v;
           }
         }

@@ -3,10 +3,10 @@
 * Training data are trace records logged on the device by plain-mode runs
   (``trs_opts.trace``): for a sampled node found blocked in round r, its head
   symbol, arity, which arguments are normal forms, and how long ago it last
-  changed; the label says whether it fired or became a normal form within
-  the next few rounds (the label horizon, 8 by default).  In learned mode a
-  node the predictor drops sleeps until the argument it waits on notifies it
-  (or a periodic sweep finds it).
+  changed; the label says whether it fired or became a normal form in the
+  next round (the label horizon, 1 by default).  In learned mode a node the
+  predictor drops sleeps until the argument it waits on notifies it (or a
+  periodic sweep finds it).
 * Training runs on the device (``trs_mlp_train``: the library's forward,
   backward and Adam kernels).
 * Parameters are stored as ``.npz`` (uint16 bfloat16 bit patterns plus the
