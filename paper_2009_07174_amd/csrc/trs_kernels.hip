@@ -962,7 +962,6 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
     const int npos = (hdr >> 12) & 15, nneg = (hdr >> 16) & 15, rootpat = (hdr >> 20) & 15;
     // new nodes, children before parents
     int q = no;
-    int bornmask = 0;  // bit j: new node j was born a normal form
     for (int j = 0; j < m; j++) {
       const int h = tab[q];
       const int sym = h & 0xffff, rci = (h >> 16) & 0x3f, bnf = (h >> 22) & 1;
@@ -988,29 +987,11 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
       if (track) p.lastchg[slot] = R.r;
       p.par[slot] = refr ? ns[refr - 1] : s;
       if (frontier && !bnf) {
-        bool keep = nready;
-        if (!keep && R.mode == 2 && ((tab[TAB_SYM + sym] >> 8) & 0xff) != 0) {
-          // its arguments: matched pattern nodes are normal forms (every
-          // node below an innermost redex is), new ones by their born_nf flag
-          int bits = 0;
-#pragma unroll
-          for (int o = 0; o < 5; o++) {
-            if (o >= ar2) {
-              bits |= 1 << o;
-            } else if (o < A) {
-              const int v = tab[q + 1 + o];
-              if (v >= 0 || ((bornmask >> (-1 - v)) & 1)) bits |= 1 << o;
-            }
-          }
-          C.mlp++;
-          keep = gate_keep(L, a.gate_off, sym, bits, 0);
-          C.keep += keep;
-        }
-        if (keep) {
-          // (learned mode: a node the predictor keeps carries this round's
-          // notification stamp, like every other queued constructor)
-          if (!nready) p.qstamp[slot] = R.stamp;
-          if (nready && R.cbuf >= 0)
+        // a new node that is not ready waits on new arguments whose parent
+        // hint is this node: notification reports them exactly, so it is
+        // not queued (nor, in learned mode, put to the predictor)
+        if (nready) {
+          if (R.cbuf >= 0)
             qpush_cont(L, R.cbuf, slot, N);  // examined later in this round
           else
             qpush(L, L.qf, slot, N);  // examined next round (retires its own marker)
@@ -1018,7 +999,6 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
           qpush(L, L.qr, slot, N);
         }
       }
-      bornmask |= bnf << j;
       q += 1 + ar2;
     }
     // the redex root is overwritten in place
@@ -1064,29 +1044,12 @@ __device__ __forceinline__ void process_slot(const RoundArgs &a, const Lds &L, c
       } else {
         if (memo) p.state[s] = (uint8_t)ST_ACTIVE;  // the arguments changed: drop the memo
         if (frontier) {
-          bool keep = root_ready;
-          if (!keep && R.mode == 2 && ((tab[TAB_SYM + rsym] >> 8) & 0xff) != 0) {
-            int bits = 0;
-#pragma unroll
-            for (int o = 0; o < 5; o++) {
-              if (o >= rar) {
-                bits |= 1 << o;
-              } else if (o < A) {
-                const int v = tab[ro + o];
-                if (v >= 0 || ((bornmask >> (-1 - v)) & 1)) bits |= 1 << o;
-              }
-            }
-            C.mlp++;
-            keep = gate_keep(L, a.gate_off, rsym, bits, 0);
-            C.keep += keep;
-            if (!keep)  // sleeps on its first argument not in normal form
-              p.state[s] = (uint8_t)(ST_ACTIVE | ((__builtin_ctz(~bits) + 1) << ST_MEMO_SHIFT));
-          }
-          // (learned mode: through the notification stamp, which an argument
-          // that became a normal form this round may also take)
+          // a root rewritten into a term that is not ready waits on new
+          // arguments whose parent hint is the root: notification reports
+          // them exactly, so it is not queued (nor put to the predictor)
           if (root_ready && R.cbuf >= 0)
             qpush_cont(L, R.cbuf, s, N);  // ready again: examined later in this round
-          else if (keep && (R.mode != 2 || notify_parent(a, R, s)))
+          else if (root_ready)
             qpush(L, L.qf, s, N);
         }
       }
