@@ -337,12 +337,13 @@ trs_status trs_membench(int32_t device, trs_membench_result *out);
 
 /* ------------------------------------------------------------------------
  * Frontier predictor (TRS_MODE_LEARNED).  Not part of the paper: a small
- * network that predicts, for a node found blocked in a round (an argument
- * not yet a normal form), whether it will fire or become a normal form soon
- * (within the label horizon); only nodes it keeps are examined in the next
- * round, the others when the argument they wait on becomes a normal form
- * (parent notification) or at the next full sweep, and a full sweep still
- * confirms the normal form (so results stay exact).
+ * network that predicts, for a node examined and found blocked in a round
+ * (an argument not yet a normal form), whether it will fire or become a
+ * normal form in the next round (the label horizon); only nodes it keeps
+ * are examined in the next round, the others when the argument they wait on
+ * becomes a normal form (parent notification) or at the next full sweep,
+ * and a full sweep still confirms the normal form (so results stay exact).
+ * Nodes created or rewritten blocked are left to notification alone.
  *
  *   x  = [E[sym] (16), arity/8, c_0..c_4, bucket(age)/15, 0]       (24)
  *   h1 = relu(W1 x + b1) (32);  h2 = relu(W2 h1 + b2) (32)
